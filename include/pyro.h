@@ -1,0 +1,164 @@
+/*
+ * pyro.h - C ABI of libpyro, per-cell ideal-gas thermochemistry on AMD
+ * Instinct MI355X (gfx950).
+ *
+ * The library evaluates the kinetics and thermodynamics formulation of
+ * Appendix A of "Pyrometheus: Symbolic abstractions for XPU and automatically
+ * differentiated computation of combustion kinetics and thermodynamics"
+ * (arXiv:2503.24286) for many independent cells at once.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Units are SI on a mole basis: T in K, p in Pa, rho in kg/m^3, molar masses
+ * in kg/mol, concentrations in mol/m^3, production rates in mol m^-3 s^-1,
+ * activation energies in J/mol, internal energy in J/kg.
+ *
+ * Cell arrays are device pointers in structure-of-arrays layout.  Per-cell
+ * scalars (rho, T, p, e, ...) hold n contiguous values.  Per-species arrays
+ * (Y, wdot, ...) are species-major: the value of species k in cell i sits at
+ * index k*ld + i, with ld >= n (the paper's (N_s, nx, ny) layout, Sec. 4.1).
+ * The caller owns every cell array; the library never allocates or frees
+ * them.  Output arrays are overwritten for cells 0..n-1 only.
+ *
+ * Calls are asynchronous on the given HIP stream (a hipStream_t passed as
+ * void*; NULL means the default stream).  A return value of PYRO_OK means the
+ * arguments were valid and the work was enqueued; numerical trouble in a
+ * cell is not an error (NaN/Inf propagate; the Newton call reports per-cell
+ * status).  On any other return nothing was enqueued and pyro_last_error()
+ * describes the problem.  n == 0 is a valid no-op.
+ *
+ * A mechanism handle belongs to the device that was current when it was
+ * loaded; calls must be made with that device current.  Handles may be used
+ * from several threads at once; calls on one stream are ordered as usual.
+ */
+#ifndef PYRO_H
+#define PYRO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#if defined(__GNUC__)
+#define PYRO_API __attribute__((visibility("default")))
+#else
+#define PYRO_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum pyro_status {
+    PYRO_OK = 0,
+    PYRO_E_ARG = -1,          /* invalid argument (null pointer, ld < n, ...) */
+    PYRO_E_IO = -2,           /* the mechanism file cannot be read           */
+    PYRO_E_FORMAT = -3,       /* malformed or inconsistent mechanism file    */
+    PYRO_E_HIP = -4,          /* a HIP runtime call failed (no device, ...)  */
+    PYRO_E_NOMEM = -5,        /* device or host allocation failed            */
+    PYRO_E_UNSUPPORTED = -6   /* valid input outside what the kernels handle */
+};
+
+enum pyro_dtype {
+    PYRO_F64 = 0,             /* double cell arrays, double arithmetic       */
+    PYRO_F32 = 1              /* float cell arrays, float arithmetic         */
+};
+
+typedef struct pyro_mech pyro_mech;
+
+typedef struct pyro_mech_info {
+    int32_t n_species;        /* S                                           */
+    int32_t n_reactions;      /* R                                           */
+    int32_t n_elements;       /* E                                           */
+    int32_t n_third_body;     /* plain third-body reactions                  */
+    int32_t n_falloff;        /* Lindemann and Troe falloff reactions        */
+    int32_t n_params;         /* R + n_falloff Arrhenius triples             */
+    int32_t nnz_reactant;     /* nonzero nu'_kj (species, reaction) pairs     */
+    int32_t nnz_product;      /* nonzero nu''_kj pairs                       */
+    int32_t nnz_net;          /* nonzero nu_kj = nu''_kj - nu'_kj pairs      */
+    int32_t pad;
+} pyro_mech_info;
+
+/* Message of the last failed call on this thread ("" if none).  The string
+ * stays valid until the next libpyro call on the same thread. */
+PYRO_API const char* pyro_last_error(void);
+
+/*
+ * Mechanism handling
+ * ------------------
+ * pyro_mech_load parses a .pyromech version-1 file (header, species,
+ * NASA7 thermodynamics, reactions with integer stoichiometry, Arrhenius,
+ * falloff, Troe and third-body data; see the file-format description in the
+ * library sources) and uploads the tables the kernels read to the current
+ * device.  It rejects a truncated or corrupted file (checksum), an unknown
+ * version, non-finite parameters, out-of-range indices and inconsistent
+ * counts (PYRO_E_FORMAT), and mechanisms beyond the kernels' limits, such as
+ * more than three molecules on one side of a reaction (PYRO_E_UNSUPPORTED).
+ * On success *out owns host and device memory until pyro_mech_free.
+ */
+PYRO_API int pyro_mech_load(const char* path, pyro_mech** out);
+PYRO_API void pyro_mech_free(pyro_mech* mech);
+PYRO_API int pyro_mech_get_info(const pyro_mech* mech, pyro_mech_info* info);
+/* Copies the S molar masses (kg/mol) into host memory W_out[S]. */
+PYRO_API int pyro_mech_molecular_weights(const pyro_mech* mech, double* W_out);
+/* Copies the default Arrhenius triples (ln A, b, Ea) into host memory
+ * params_out[3*n_params]: rows 0..R-1 are the reactions' own (high-pressure
+ * for falloff) triples, rows R.. the falloff low-pressure triples. */
+PYRO_API int pyro_mech_arrhenius(const pyro_mech* mech, double* params_out);
+
+/*
+ * Net production rates (Appendix A.1: eq. concentrations, eq. nasa_poly,
+ * eq. gibbs, eq. rate_coeff, eq. equil_constants, eq. reaction_rates,
+ * eq. production_rates; third-body and Lindemann/Troe falloff forms for the
+ * rate coefficients the paper names but does not write).
+ *
+ *   rho[n], T[n]   density and temperature
+ *   Y[S*ld]        mass fractions (negative values count as zero; the sum is
+ *                  not required to be one)
+ *   wdot[S*ld]     output omega_k
+ *   params         device array of 3*n_params doubles (ln A, b, Ea) that
+ *                  replaces the mechanism's Arrhenius triples, or NULL
+ *   dtype          PYRO_F64: rho, T, Y, wdot are double.  PYRO_F32: they are
+ *                  float and the arithmetic is float (params stay double).
+ */
+PYRO_API int pyro_production_rates(const pyro_mech* mech, int64_t n, int64_t ld,
+                          int dtype, const void* rho, const void* T,
+                          const void* Y, void* wdot, const double* params,
+                          void* stream);
+
+/*
+ * Temperature from the mass-specific internal energy by Newton iteration
+ * (Appendix A.3.1: eq. int_energy, eq. delta_temp, eq. cv):
+ * T <- T - (Y.e(T) - e)/c_v(T), per cell, until the first update with
+ * |dT| <= rtol*|T| or max_iter updates.
+ *
+ *   e[n]           internal energy (J/kg)
+ *   Y[S*ld]        mass fractions (used as given)
+ *   T_guess        device array of n initial guesses, or NULL to start every
+ *                  cell from T_guess_value
+ *   T_out[n]       result
+ *   status[n]      number of updates taken, negated when rtol was not met
+ *   max_iter       >= 1; rtol >= 0
+ */
+PYRO_API int pyro_temperature(const pyro_mech* mech, int64_t n, int64_t ld,
+                     const double* e, const double* Y, const double* T_guess,
+                     double T_guess_value, double* T_out, int32_t* status,
+                     int max_iter, double rtol, void* stream);
+
+/* Equation of state (Appendix A.1, eq. eos): rho = p W/(R T) and
+ * p = rho R T/W with W = (sum_k Y_k/W_k)^-1.  FP64 cell arrays. */
+PYRO_API int pyro_density(const pyro_mech* mech, int64_t n, int64_t ld, const double* p,
+                 const double* T, const double* Y, double* rho_out, void* stream);
+PYRO_API int pyro_pressure(const pyro_mech* mech, int64_t n, int64_t ld,
+                  const double* rho, const double* T, const double* Y,
+                  double* p_out, void* stream);
+
+/* Mixture internal energy e = sum_k Y_k (h_k - R T)/W_k in J/kg
+ * (Appendix A.3.1, eq. int_energy).  FP64 cell arrays. */
+PYRO_API int pyro_internal_energy(const pyro_mech* mech, int64_t n, int64_t ld,
+                         const double* T, const double* Y, double* e_out,
+                         void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PYRO_H */

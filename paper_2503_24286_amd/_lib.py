@@ -1,0 +1,86 @@
+"""ctypes loader of libpyro.so with the signatures of include/pyro.h.
+
+The library must have been built (``__graft_entry__.build()`` or
+``python -m paper_2503_24286_amd.build``); there is no fallback.
+"""
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpyro.so")
+
+PYRO_OK = 0
+PYRO_E_ARG = -1
+PYRO_E_IO = -2
+PYRO_E_FORMAT = -3
+PYRO_E_HIP = -4
+PYRO_E_NOMEM = -5
+PYRO_E_UNSUPPORTED = -6
+STATUS_NAMES = {0: "PYRO_OK", -1: "PYRO_E_ARG", -2: "PYRO_E_IO", -3: "PYRO_E_FORMAT",
+                -4: "PYRO_E_HIP", -5: "PYRO_E_NOMEM", -6: "PYRO_E_UNSUPPORTED"}
+PYRO_F64 = 0
+PYRO_F32 = 1
+
+
+class PyroError(RuntimeError):
+    def __init__(self, code, message):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {message}")
+        self.code = code
+
+
+class MechInfo(ctypes.Structure):
+    _fields_ = [("n_species", ctypes.c_int32), ("n_reactions", ctypes.c_int32),
+                ("n_elements", ctypes.c_int32), ("n_third_body", ctypes.c_int32),
+                ("n_falloff", ctypes.c_int32), ("n_params", ctypes.c_int32),
+                ("nnz_reactant", ctypes.c_int32), ("nnz_product", ctypes.c_int32),
+                ("nnz_net", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
+_P = ctypes.c_void_p
+_I64 = ctypes.c_int64
+_I = ctypes.c_int
+_D = ctypes.c_double
+
+SIGNATURES = {
+    "pyro_last_error": (ctypes.c_char_p, []),
+    "pyro_mech_load": (_I, [ctypes.c_char_p, ctypes.POINTER(_P)]),
+    "pyro_mech_free": (None, [_P]),
+    "pyro_mech_get_info": (_I, [_P, ctypes.POINTER(MechInfo)]),
+    "pyro_mech_molecular_weights": (_I, [_P, _P]),
+    "pyro_mech_arrhenius": (_I, [_P, _P]),
+    "pyro_production_rates": (_I, [_P, _I64, _I64, _I, _P, _P, _P, _P, _P, _P]),
+    "pyro_temperature": (_I, [_P, _I64, _I64, _P, _P, _P, _D, _P, _P, _I, _D, _P]),
+    "pyro_density": (_I, [_P, _I64, _I64, _P, _P, _P, _P, _P]),
+    "pyro_pressure": (_I, [_P, _I64, _I64, _P, _P, _P, _P, _P]),
+    "pyro_internal_energy": (_I, [_P, _I64, _I64, _P, _P, _P, _P]),
+}
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(
+                f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                "(there is no CPU fallback)")
+        handle = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(handle, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = handle
+    return _lib
+
+
+def last_error():
+    return lib().pyro_last_error().decode()
+
+
+def check(code):
+    if code != PYRO_OK:
+        raise PyroError(code, last_error())
+    return code

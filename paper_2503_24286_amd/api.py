@@ -1,0 +1,168 @@
+"""Torch-facing wrappers of libpyro: argument marshalling only.
+
+Every array is a CUDA (HIP) tensor; per-species arrays are species-major
+``(S, n)`` views whose row stride is ``ld`` (any ``ld >= n``), per-cell arrays
+are contiguous ``(n,)``.  Calls are enqueued on torch's current stream.
+"""
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import PyroError, check, lib  # noqa: F401
+
+
+def _stream(device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _species_major(Y, S, dtype, name):
+    if Y.dim() != 2 or Y.shape[0] != S:
+        raise ValueError(f"{name} must have shape (S={S}, n)")
+    if Y.dtype != dtype or not Y.is_cuda:
+        raise ValueError(f"{name} must be a {dtype} CUDA tensor")
+    if Y.stride(1) != 1 or (S > 1 and Y.stride(0) < Y.shape[1]):
+        raise ValueError(f"{name} must have unit cell stride and row stride >= n")
+    return Y.stride(0) if S > 1 else max(Y.shape[1], 1)
+
+
+def _cells(x, n, dtype, name):
+    if x.dim() != 1 or x.shape[0] != n or x.dtype != dtype or not x.is_cuda:
+        raise ValueError(f"{name} must be a contiguous ({n},) {dtype} CUDA tensor")
+    if x.stride(0) != 1:
+        raise ValueError(f"{name} must be contiguous")
+
+
+class Mechanism:
+    """A loaded mechanism (``pyro_mech_load``) on the current device."""
+
+    def __init__(self, path):
+        handle = ctypes.c_void_p()
+        check(lib().pyro_mech_load(os.fsencode(path), ctypes.byref(handle)))
+        self._h = handle
+        info = _lib.MechInfo()
+        check(lib().pyro_mech_get_info(handle, ctypes.byref(info)))
+        self.n_species = info.n_species
+        self.n_reactions = info.n_reactions
+        self.n_elements = info.n_elements
+        self.n_third_body = info.n_third_body
+        self.n_falloff = info.n_falloff
+        self.n_params = info.n_params
+        self.nnz_reactant = info.nnz_reactant
+        self.nnz_product = info.nnz_product
+        self.nnz_net = info.nnz_net
+        W = np.empty(self.n_species)
+        check(lib().pyro_mech_molecular_weights(handle, W.ctypes.data_as(ctypes.c_void_p)))
+        self.molecular_weights = W
+        P = np.empty((self.n_params, 3))
+        check(lib().pyro_mech_arrhenius(handle, P.ctypes.data_as(ctypes.c_void_p)))
+        self.arrhenius = P
+        self.device = torch.cuda.current_device()
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().pyro_mech_free(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def production_rates(mech, rho, T, Y, out=None, params=None):
+    """omega (S, n) from rho (n,), T (n,), Y (S, n); FP64 or FP32 tensors."""
+    dtype = Y.dtype
+    if dtype not in (torch.float64, torch.float32):
+        raise ValueError("Y must be float64 or float32")
+    S = mech.n_species
+    n = Y.shape[1]
+    ld = _species_major(Y, S, dtype, "Y")
+    _cells(rho, n, dtype, "rho")
+    _cells(T, n, dtype, "T")
+    if out is None:
+        out = torch.empty((S, ld), dtype=dtype, device=Y.device)[:, :n]
+    if _species_major(out, S, dtype, "out") != ld:
+        raise ValueError("out must have the row stride of Y")
+    if params is not None:
+        if params.dtype != torch.float64 or params.numel() != 3 * mech.n_params:
+            raise ValueError("params must hold 3*n_params float64 values")
+        params = params.contiguous()
+    code = lib().pyro_production_rates(
+        mech.handle, n, ld, _lib.PYRO_F64 if dtype == torch.float64 else _lib.PYRO_F32,
+        _ptr(rho), _ptr(T), _ptr(Y), _ptr(out), _ptr(params), _stream(Y.device))
+    check(code)
+    return out
+
+
+def temperature(mech, e, Y, T_guess=1200.0, max_iter=50, rtol=1e-12, out=None, status=None):
+    """Newton inversion T(e, Y); returns (T, status)."""
+    S = mech.n_species
+    n = Y.shape[1]
+    ld = _species_major(Y, S, torch.float64, "Y")
+    _cells(e, n, torch.float64, "e")
+    tg = None
+    tg_value = 0.0
+    if isinstance(T_guess, torch.Tensor):
+        _cells(T_guess, n, torch.float64, "T_guess")
+        tg = T_guess
+    else:
+        tg_value = float(T_guess)
+    if out is None:
+        out = torch.empty(n, dtype=torch.float64, device=Y.device)
+    if status is None:
+        status = torch.empty(n, dtype=torch.int32, device=Y.device)
+    check(lib().pyro_temperature(mech.handle, n, ld, _ptr(e), _ptr(Y), _ptr(tg), tg_value,
+                                 _ptr(out), _ptr(status), int(max_iter), float(rtol),
+                                 _stream(Y.device)))
+    return out, status
+
+
+def density(mech, p, T, Y, out=None):
+    S = mech.n_species
+    n = Y.shape[1]
+    ld = _species_major(Y, S, torch.float64, "Y")
+    _cells(p, n, torch.float64, "p")
+    _cells(T, n, torch.float64, "T")
+    if out is None:
+        out = torch.empty(n, dtype=torch.float64, device=Y.device)
+    check(lib().pyro_density(mech.handle, n, ld, _ptr(p), _ptr(T), _ptr(Y), _ptr(out),
+                             _stream(Y.device)))
+    return out
+
+
+def pressure(mech, rho, T, Y, out=None):
+    S = mech.n_species
+    n = Y.shape[1]
+    ld = _species_major(Y, S, torch.float64, "Y")
+    _cells(rho, n, torch.float64, "rho")
+    _cells(T, n, torch.float64, "T")
+    if out is None:
+        out = torch.empty(n, dtype=torch.float64, device=Y.device)
+    check(lib().pyro_pressure(mech.handle, n, ld, _ptr(rho), _ptr(T), _ptr(Y), _ptr(out),
+                              _stream(Y.device)))
+    return out
+
+
+def internal_energy(mech, T, Y, out=None):
+    S = mech.n_species
+    n = Y.shape[1]
+    ld = _species_major(Y, S, torch.float64, "Y")
+    _cells(T, n, torch.float64, "T")
+    if out is None:
+        out = torch.empty(n, dtype=torch.float64, device=Y.device)
+    check(lib().pyro_internal_energy(mech.handle, n, ld, _ptr(T), _ptr(Y), _ptr(out),
+                                     _stream(Y.device)))
+    return out

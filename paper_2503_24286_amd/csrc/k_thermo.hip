@@ -1,0 +1,176 @@
+// Per-cell mixture thermodynamics: Newton inversion of T from the internal
+// energy (Appendix A.3.1: eq. int_energy, eq. delta_temp, eq. cv), the
+// mixture internal energy, and the equation of state (Appendix A.1, eq. eos).
+//
+// The mixture energy is linear in the NASA7 coefficients, so one pass over
+// the species folds them, weighted by X_k = Y_k/W_k, into six mixture
+// coefficients per range (and per distinct T_mid); every Newton iterate then
+// costs a handful of FMAs instead of a pass over the species:
+//   e(T)   = R [ A1 T + A2 T^2/2 + A3 T^3/3 + A4 T^4/4 + A5 T^5/5 + A6 - T sum X ]
+//   c_v(T) = R [ A1 + A2 T + A3 T^2 + A4 T^3 + A5 T^4 - sum X ]
+// with A_m = sum_k X_k a_m,k over the species whose range holds T.  The pass
+// reads Y once (coalesced), so the kernel is bound by HBM bandwidth.
+#include "pyro_internal.h"
+
+namespace pyro {
+namespace {
+
+constexpr int kBlock = 256;
+
+struct Mixture {
+    double A[kMaxTmidGroups][2][6];
+    double xsum;
+};
+
+template <int NG>
+__device__ inline void fold(const DevMech& m, const double* __restrict__ Y, int64_t ld,
+                            int64_t c, Mixture& mx) {
+#pragma unroll
+    for (int g = 0; g < NG; ++g)
+#pragma unroll
+        for (int r = 0; r < 2; ++r)
+#pragma unroll
+            for (int q = 0; q < 6; ++q) mx.A[g][r][q] = 0.0;
+    mx.xsum = 0.0;
+    for (int k = 0; k < m.S; ++k) {
+        const NewtonSpecies& s = m.newton[k];
+        const double X = Y[size_t(k) * ld + c] * s.inv_w;
+        mx.xsum += X;
+#pragma unroll
+        for (int g = 0; g < NG; ++g) {
+            if (s.group == g) {
+#pragma unroll
+                for (int q = 0; q < 6; ++q) {
+                    mx.A[g][0][q] = fma(X, s.lo[q], mx.A[g][0][q]);
+                    mx.A[g][1][q] = fma(X, s.hi[q], mx.A[g][1][q]);
+                }
+            }
+        }
+    }
+}
+
+// e(T)/R and c_v(T)/R of the folded mixture.
+template <int NG>
+__device__ inline void energy(const DevMech& m, const Mixture& mx, double T, double& e_R,
+                              double& cv_R) {
+    double h = 0.0, cp = 0.0;
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+        const bool low = T <= m.t_mid_group[g];
+        double a[6];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) a[q] = low ? mx.A[g][0][q] : mx.A[g][1][q];
+        h += a[5] + T * (a[0] + T * (a[1] * 0.5 + T * (a[2] * (1.0 / 3.0) +
+                              T * (a[3] * 0.25 + T * (a[4] * 0.2)))));
+        cp += a[0] + T * (a[1] + T * (a[2] + T * (a[3] + T * a[4])));
+    }
+    e_R = h - T * mx.xsum;
+    cv_R = cp - mx.xsum;
+}
+
+template <int NG>
+__global__ __launch_bounds__(kBlock) void newton_kernel(
+    DevMech m, int64_t n, int64_t ld, const double* __restrict__ e,
+    const double* __restrict__ Y, const double* __restrict__ Tg, double Tg_value,
+    double* __restrict__ T_out, int32_t* __restrict__ status, int max_iter, double rtol) {
+    const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+    const bool valid = i < n;
+    const int64_t c = valid ? i : n - 1;
+    Mixture mx;
+    fold<NG>(m, Y, ld, c, mx);
+    const double target = e[c] * (1.0 / kGasConstant);
+    double T = Tg ? Tg[c] : Tg_value;
+    int32_t st = -max_iter;
+    bool active = valid;
+    for (int it = 0; it < max_iter; ++it) {
+        if (!__any(active)) break;
+        if (active) {
+            double eR, cvR;
+            energy<NG>(m, mx, T, eR, cvR);
+            const double dT = -(eR - target) / cvR;
+            T += dT;
+            if (fabs(dT) <= rtol * fabs(T)) {
+                st = it + 1;
+                active = false;
+            }
+        }
+    }
+    if (valid) {
+        T_out[i] = T;
+        status[i] = st;
+    }
+}
+
+template <int NG>
+__global__ __launch_bounds__(kBlock) void energy_kernel(DevMech m, int64_t n, int64_t ld,
+                                                        const double* __restrict__ T,
+                                                        const double* __restrict__ Y,
+                                                        double* __restrict__ out) {
+    const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+    if (i >= n) return;
+    Mixture mx;
+    fold<NG>(m, Y, ld, i, mx);
+    double eR, cvR;
+    energy<NG>(m, mx, T[i], eR, cvR);
+    out[i] = eR * kGasConstant;
+}
+
+// mode 0: a = p, out = rho; mode 1: a = rho, out = p
+__global__ __launch_bounds__(kBlock) void eos_kernel(DevMech m, int64_t n, int64_t ld, int mode,
+                                                     const double* __restrict__ a,
+                                                     const double* __restrict__ T,
+                                                     const double* __restrict__ Y,
+                                                     double* __restrict__ out) {
+    const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+    if (i >= n) return;
+    double x = 0.0;
+    for (int k = 0; k < m.S; ++k) x += Y[size_t(k) * ld + i] * m.newton[k].inv_w;
+    // x = 1/W (mixture)
+    const double RT = kGasConstant * T[i];
+    out[i] = mode == 0 ? a[i] / (x * RT) : a[i] * RT * x;
+}
+
+unsigned grid(int64_t n) { return unsigned((n + kBlock - 1) / kBlock); }
+
+}  // namespace
+
+hipError_t launch_temperature(const pyro_mech* m, int64_t n, int64_t ld, const double* e,
+                              const double* Y, const double* T_guess, double T_guess_value,
+                              double* T_out, int32_t* status, int max_iter, double rtol,
+                              hipStream_t stream) {
+    switch (m->dev.n_groups) {
+        case 1:
+            hipLaunchKernelGGL(newton_kernel<1>, dim3(grid(n)), dim3(kBlock), 0, stream, m->dev, n,
+                               ld, e, Y, T_guess, T_guess_value, T_out, status, max_iter, rtol);
+            break;
+        case 2:
+            hipLaunchKernelGGL(newton_kernel<2>, dim3(grid(n)), dim3(kBlock), 0, stream, m->dev, n,
+                               ld, e, Y, T_guess, T_guess_value, T_out, status, max_iter, rtol);
+            break;
+        default:
+            hipLaunchKernelGGL(newton_kernel<kMaxTmidGroups>, dim3(grid(n)), dim3(kBlock), 0,
+                               stream, m->dev, n, ld, e, Y, T_guess, T_guess_value, T_out, status,
+                               max_iter, rtol);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_internal_energy(const pyro_mech* m, int64_t n, int64_t ld, const double* T,
+                                  const double* Y, double* e_out, hipStream_t stream) {
+    if (m->dev.n_groups == 1)
+        hipLaunchKernelGGL(energy_kernel<1>, dim3(grid(n)), dim3(kBlock), 0, stream, m->dev, n, ld,
+                           T, Y, e_out);
+    else
+        hipLaunchKernelGGL(energy_kernel<kMaxTmidGroups>, dim3(grid(n)), dim3(kBlock), 0, stream,
+                           m->dev, n, ld, T, Y, e_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_eos(const pyro_mech* m, int64_t n, int64_t ld, int mode, const double* a,
+                      const double* T, const double* Y, double* out, hipStream_t stream) {
+    hipLaunchKernelGGL(eos_kernel, dim3(grid(n)), dim3(kBlock), 0, stream, m->dev, n, ld, mode, a,
+                       T, Y, out);
+    return hipGetLastError();
+}
+
+}  // namespace pyro

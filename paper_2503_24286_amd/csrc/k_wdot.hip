@@ -1,0 +1,235 @@
+// Net production rates omega(rho, T, Y) for a tile of 64 cells per
+// workgroup (Appendix A.1: eq. concentrations, eq. nasa_poly, eq. gibbs,
+// eq. rate_coeff, eq. equil_constants, eq. reaction_rates,
+// eq. production_rates).
+//
+// Mapping on CDNA4: one cell per lane, four wavefronts per workgroup, all
+// lanes of a wave on the same species or reaction at the same time, so every
+// mechanism-table read is wave-uniform and goes through the scalar cache.
+//
+//  1. species phase: each wave computes, for the species it owns,
+//     C_k = rho max(Y_k, 0)/W_k and G_k = exp(g0_k/(R T)) and parks the pair
+//     in LDS (row k, 16 bytes per lane);
+//  2. reaction phase, in chunks of 16 reactions (4 per wave): the forward
+//     coefficient k = exp(ln A + b ln T - Ea/(R T)), third-body and falloff
+//     corrections, and the rate of progress
+//         q = k prod_r C_r - k (R T/p0)^dnu prod_p (C_p G_p) / prod_r G_r,
+//     which is eq. reaction_rates with 1/K = (R T/p0)^dnu prod G^nu; q goes to
+//     an LDS slot of the chunk (double buffered);
+//  3. after the chunk barrier, each wave adds nu_kj q_j into register
+//     accumulators of the species it owns, in a fixed order (deterministic);
+//  4. the owners write omega_k for the 64 cells (coalesced 512-byte rows).
+//
+// The equilibrium constant of every reaction thus costs products of S
+// per-species exponentials instead of one exponential per reaction.
+#include "pyro_internal.h"
+
+namespace pyro {
+namespace {
+
+constexpr int kCgStride = kTile * 16;           // bytes per species row of the C/G tile
+constexpr int kQBuf = kChunk * kTile * 8;       // bytes per chunk buffer
+
+__device__ inline double2 lds_cg(const unsigned char* lds, int off, int lane) {
+    return *reinterpret_cast<const double2*>(lds + off + lane * 16);
+}
+
+// Reaction rate of progress of one reaction for the calling lane's cell.
+__device__ inline double rate_of_progress(const DevMech& m, const RxnRec& r,
+                                          const double* __restrict__ params,
+                                          const unsigned char* lds, int lane,
+                                          double Tc, double lnT, double invT,
+                                          double invRT, double rtp, double irtp) {
+    const double* pr = params + 3 * r.prow;
+    double kf = exp(pr[0] + pr[1] * lnT - pr[2] * invRT);
+    double M = 1.0;
+    if (r.cls >= kThirdBody) {
+        // [M] = sum_k eps_k C_k
+        const double* e = m.eff + size_t(r.pd) * m.s_pad;
+        double acc = 0.0;
+        for (int k = 0; k < m.s_pad; k += 8) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                acc = fma(e[k + u], lds_cg(lds, (k + u) * kCgStride, lane).x, acc);
+        }
+        M = acc;
+    }
+    if (r.cls >= kLindemann) {
+        const double* pl = params + 3 * (m.R + r.fo);
+        const double k0 = exp(pl[0] + pl[1] * lnT - pl[2] * invRT);
+        const double Pr = k0 * M / kf;
+        double F = 1.0;
+        if (r.cls == kTroe) {
+            const FalloffRec f = m.falloff[r.fo];
+            double Fcent = (1.0 - f.alpha) * exp(Tc * f.a3) + f.alpha * exp(Tc * f.a1) +
+                           exp(f.a2 * invT);
+            Fcent = fmax(Fcent, 1e-300);
+            const double lfc = log10(Fcent);
+            const double c = -0.4 - 0.67 * lfc;
+            const double nn = 0.75 - 1.27 * lfc;
+            const double x = log10(fmax(Pr, 1e-300)) + c;
+            const double f1 = x / (nn - 0.14 * x);
+            F = exp10(lfc / (1.0 + f1 * f1));
+        }
+        kf = kf * (Pr / (1.0 + Pr)) * F;
+    }
+    // forward term k prod_r C_r
+    double2 a = lds_cg(lds, r.r[0], lane);
+    double cr = a.x, gr = a.y;
+    if (r.nr > 1) {
+        const double2 b = lds_cg(lds, r.r[1], lane);
+        cr *= b.x;
+        gr *= b.y;
+        if (r.nr > 2) {
+            const double2 c = lds_cg(lds, r.r[2], lane);
+            cr *= c.x;
+            gr *= c.y;
+        }
+    }
+    double q = kf * cr;
+    if (r.rev) {
+        double2 p = lds_cg(lds, r.p[0], lane);
+        double cgp = p.x * p.y;
+        if (r.np > 1) {
+            const double2 b = lds_cg(lds, r.p[1], lane);
+            cgp *= b.x * b.y;
+            if (r.np > 2) {
+                const double2 c = lds_cg(lds, r.p[2], lane);
+                cgp *= c.x * c.y;
+            }
+        }
+        double pw = 1.0;
+        if (r.dnu > 0)
+            for (int i = 0; i < r.dnu; ++i) pw *= rtp;
+        else
+            for (int i = 0; i < -r.dnu; ++i) pw *= irtp;
+        q -= kf * pw * cgp / gr;
+    }
+    if (r.cls == kThirdBody) q *= M;
+    return q;
+}
+
+template <int MAXOWN>
+__global__ __launch_bounds__(kWaves * 64) void wdot_f64_kernel(
+    DevMech m, int64_t n, int64_t ld, const double* __restrict__ rho,
+    const double* __restrict__ T, const double* __restrict__ Y,
+    double* __restrict__ wdot, const double* __restrict__ params) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t cell = int64_t(blockIdx.x) * kTile + lane;
+    const bool valid = cell < n;
+    const int64_t c = valid ? cell : n - 1;
+
+    const double Tc = T[c];
+    const double rc = rho[c];
+    const double lnT = log(Tc);
+    const double invT = 1.0 / Tc;
+    const double invRT = invT * (1.0 / kGasConstant);
+    const double rtp = kGasConstant * Tc / kOneAtm;
+    const double irtp = 1.0 / rtp;
+    const double omlnT = 1.0 - lnT;
+
+    // ---- species phase
+    const int nown = m.n_own[w];
+    const int32_t* own = m.own + w * kMaxOwn;
+    for (int i = 0; i < nown; ++i) {
+        const int k = own[i];
+        const SpeciesRec& s = m.species[k];
+        const double y = Y[size_t(k) * ld + c];
+        const double Ck = rc * fmax(y, 0.0) * s.inv_w;
+        const bool low = Tc <= s.t_mid;
+        double g[7];
+#pragma unroll
+        for (int q = 0; q < 7; ++q) g[q] = low ? s.lo[q] : s.hi[q];
+        const double gRT = g[0] * omlnT + g[6] + g[5] * invT +
+                           Tc * (g[1] + Tc * (g[2] + Tc * (g[3] + Tc * g[4])));
+        *reinterpret_cast<double2*>(lds + k * kCgStride + lane * 16) = make_double2(Ck, exp(gRT));
+    }
+    if (w == 0)
+        for (int k = m.S; k < m.s_pad; ++k)
+            *reinterpret_cast<double2*>(lds + k * kCgStride + lane * 16) = make_double2(0.0, 0.0);
+    __syncthreads();
+
+    // ---- reaction chunks and gathering
+    double acc[MAXOWN];
+#pragma unroll
+    for (int i = 0; i < MAXOWN; ++i) acc[i] = 0.0;
+    unsigned char* qbase = lds + size_t(m.s_pad) * kCgStride;
+    for (int ch = 0; ch < m.n_chunks; ++ch) {
+        unsigned char* qb = qbase + (ch & 1) * kQBuf;
+        const RxnRec* rb = m.rxn + (size_t(ch) * kWaves + w) * kRxnPerWave;
+        for (int t = 0; t < kRxnPerWave; ++t) {
+            const RxnRec r = rb[t];
+            if (r.cls == kNoReaction) continue;
+            const double q = rate_of_progress(m, r, params, lds, lane, Tc, lnT, invT, invRT, rtp, irtp);
+            *reinterpret_cast<double*>(qb + r.qoff + lane * 8) = q;
+        }
+        __syncthreads();
+        const int32_t* gp = m.gptr + (size_t(ch) * kWaves + w) * (kMaxOwn + 1);
+#pragma unroll
+        for (int i = 0; i < MAXOWN; ++i) {
+            if (i < nown) {
+                double a = acc[i];
+                const int e1 = gp[i + 1];
+                for (int e = gp[i]; e < e1; ++e) {
+                    const GatherEntry g = m.gent[e];
+                    a = fma(g.nu, *reinterpret_cast<const double*>(qb + g.qoff + lane * 8), a);
+                }
+                acc[i] = a;
+            }
+        }
+    }
+    if (valid) {
+#pragma unroll
+        for (int i = 0; i < MAXOWN; ++i)
+            if (i < nown) wdot[size_t(own[i]) * ld + cell] = acc[i];
+    }
+}
+
+template <int MAXOWN>
+hipError_t launch_f64(const pyro_mech* m, int64_t n, int64_t ld, const double* rho,
+                      const double* T, const double* Y, double* wdot,
+                      const double* params, hipStream_t stream) {
+    const size_t lds = production_rates_lds_bytes(m);
+    const int64_t blocks = (n + kTile - 1) / kTile;
+    hipLaunchKernelGGL(wdot_f64_kernel<MAXOWN>, dim3(unsigned(blocks)), dim3(kWaves * 64),
+                       lds, stream, m->dev, n, ld, rho, T, Y, wdot,
+                       params ? params : m->dev.params);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+size_t production_rates_lds_bytes(const pyro_mech* m) {
+    const int s_pad = (m->S + 7) / 8 * 8;
+    return size_t(s_pad) * kCgStride + 2 * size_t(kQBuf);
+}
+
+hipError_t prepare_production_rates(const pyro_mech* m) {
+    const int lds = int(production_rates_lds_bytes(m));
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&wdot_f64_kernel<16>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute(reinterpret_cast<const void*>(&wdot_f64_kernel<32>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute(reinterpret_cast<const void*>(&wdot_f64_kernel<64>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    return e;
+}
+
+hipError_t launch_production_rates(const pyro_mech* m, int64_t n, int64_t ld, int dtype,
+                                   const void* rho, const void* T, const void* Y,
+                                   void* wdot, const double* params, hipStream_t stream) {
+    (void)dtype;
+    const double* r = static_cast<const double*>(rho);
+    const double* t = static_cast<const double*>(T);
+    const double* y = static_cast<const double*>(Y);
+    double* o = static_cast<double*>(wdot);
+    if (m->max_own <= 16) return launch_f64<16>(m, n, ld, r, t, y, o, params, stream);
+    if (m->max_own <= 32) return launch_f64<32>(m, n, ld, r, t, y, o, params, stream);
+    return launch_f64<64>(m, n, ld, r, t, y, o, params, stream);
+}
+
+}  // namespace pyro

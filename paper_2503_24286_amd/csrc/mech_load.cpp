@@ -1,0 +1,451 @@
+// Loader of .pyromech version-1 mechanism files and builder of the device
+// tables the kernels read.
+//
+// File layout (little endian): a 48-byte header
+//   char[8] "PYROMECH", u32 version (1), u32 S, u32 R, u32 E,
+//   u32 n_third_body, u32 n_falloff, u32 reactant nnz, u32 product nnz,
+//   u64 payload bytes,
+// the payload arrays, each zero padded to 8 bytes,
+//   f64 element_weight[E], i32 composition[E][S], f64 W[S],
+//   f64 T_range[S][3] (T_low, T_mid, T_high), f64 nasa[S][2][7],
+//   i32 rtype[R] (0 elementary, 1 third-body, 2 Lindemann, 3 Troe),
+//   i32 reversible[R], f64 arrhenius[R][3] (ln A, b, Ea in J/mol),
+//   i32 reac_ptr[R+1], reac_species[nnz], reac_nu[nnz],
+//   i32 prod_ptr[R+1], prod_species[nnz], prod_nu[nnz],
+//   i32 falloff_reaction[n_falloff], f64 falloff_low[n_falloff][3],
+//   f64 troe[n_falloff][4] (alpha, T***, T*, T**),
+//   f64 efficiency[n_third_body + n_falloff][S],
+// and a trailing u64 FNV-1a hash of every preceding byte.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <fstream>
+#include <numeric>
+#include <sstream>
+
+#include "pyro_internal.h"
+
+namespace pyro {
+namespace {
+
+struct Reader {
+    const uint8_t* data;
+    size_t size;
+    size_t pos;
+    bool ok = true;
+
+    template <class T>
+    std::vector<T> take(size_t count) {
+        std::vector<T> out(count);
+        const size_t bytes = count * sizeof(T);
+        if (!ok || pos + bytes > size) {
+            ok = false;
+            return out;
+        }
+        if (bytes) std::memcpy(out.data(), data + pos, bytes);
+        pos += bytes + ((8 - bytes % 8) % 8);
+        return out;
+    }
+};
+
+uint64_t fnv1a64(const uint8_t* p, size_t n) {
+    uint64_t h = 0xcbf29ce484222325ull;
+    for (size_t i = 0; i < n; ++i) {
+        h ^= p[i];
+        h *= 0x100000001b3ull;
+    }
+    return h;
+}
+
+bool all_finite(const std::vector<double>& v) {
+    for (double x : v)
+        if (!std::isfinite(x)) return false;
+    return true;
+}
+
+// Parsed file contents, in file order.
+struct Parsed {
+    uint32_t S, R, E, n_tb, n_fo;
+    std::vector<double> ew, W, trange, nasa, arrh, low, troe, eff;
+    std::vector<int32_t> comp, rtype, rev, rp, rs, rn, pp, ps, pn, fo;
+};
+
+int parse(const std::vector<uint8_t>& blob, Parsed& f) {
+    if (blob.size() < 56) return fail(PYRO_E_FORMAT, "mechanism file too short");
+    if (std::memcmp(blob.data(), "PYROMECH", 8) != 0)
+        return fail(PYRO_E_FORMAT, "bad magic (not a .pyromech file)");
+    uint32_t hdr[8];
+    uint64_t payload;
+    std::memcpy(hdr, blob.data() + 8, 32);
+    std::memcpy(&payload, blob.data() + 40, 8);
+    if (hdr[0] != 1)
+        return fail(PYRO_E_FORMAT, "unsupported .pyromech version " + std::to_string(hdr[0]));
+    if (payload > blob.size() || blob.size() != 48 + payload + 8)
+        return fail(PYRO_E_FORMAT, "file size does not match the header");
+    uint64_t stored;
+    std::memcpy(&stored, blob.data() + 48 + payload, 8);
+    if (stored != fnv1a64(blob.data(), 48 + payload))
+        return fail(PYRO_E_FORMAT, "checksum mismatch (corrupted file)");
+    f.S = hdr[1];
+    f.R = hdr[2];
+    f.E = hdr[3];
+    f.n_tb = hdr[4];
+    f.n_fo = hdr[5];
+    const uint32_t nnz_r = hdr[6], nnz_p = hdr[7];
+    if (f.S == 0 || f.S > 4096 || f.R > (1u << 20) || f.E > 64 ||
+        f.n_tb + f.n_fo > f.R || nnz_r > 16 * (f.R + 1) || nnz_p > 16 * (f.R + 1))
+        return fail(PYRO_E_FORMAT, "implausible counts in the header");
+    Reader rd{blob.data(), 48 + payload, 48};
+    f.ew = rd.take<double>(f.E);
+    f.comp = rd.take<int32_t>(size_t(f.E) * f.S);
+    f.W = rd.take<double>(f.S);
+    f.trange = rd.take<double>(size_t(f.S) * 3);
+    f.nasa = rd.take<double>(size_t(f.S) * 14);
+    f.rtype = rd.take<int32_t>(f.R);
+    f.rev = rd.take<int32_t>(f.R);
+    f.arrh = rd.take<double>(size_t(f.R) * 3);
+    f.rp = rd.take<int32_t>(f.R + 1);
+    f.rs = rd.take<int32_t>(nnz_r);
+    f.rn = rd.take<int32_t>(nnz_r);
+    f.pp = rd.take<int32_t>(f.R + 1);
+    f.ps = rd.take<int32_t>(nnz_p);
+    f.pn = rd.take<int32_t>(nnz_p);
+    f.fo = rd.take<int32_t>(f.n_fo);
+    f.low = rd.take<double>(size_t(f.n_fo) * 3);
+    f.troe = rd.take<double>(size_t(f.n_fo) * 4);
+    f.eff = rd.take<double>(size_t(f.n_tb + f.n_fo) * f.S);
+    if (!rd.ok || rd.pos != 48 + payload)
+        return fail(PYRO_E_FORMAT, "payload size does not match the header counts");
+
+    // values
+    for (double w : f.W)
+        if (!(std::isfinite(w) && w > 0)) return fail(PYRO_E_FORMAT, "non-positive or non-finite molar mass");
+    if (!all_finite(f.ew) || !all_finite(f.trange) || !all_finite(f.nasa) ||
+        !all_finite(f.arrh) || !all_finite(f.low) || !all_finite(f.troe) || !all_finite(f.eff))
+        return fail(PYRO_E_FORMAT, "non-finite parameter in the mechanism");
+    for (uint32_t k = 0; k < f.S; ++k) {
+        const double* t = &f.trange[3 * k];
+        if (!(t[0] > 0 && t[0] < t[1] && t[1] < t[2]))
+            return fail(PYRO_E_FORMAT, "species " + std::to_string(k) + ": bad NASA7 temperature ranges");
+    }
+    uint32_t n_tb = 0, n_fo = 0;
+    for (uint32_t j = 0; j < f.R; ++j) {
+        if (f.rtype[j] < 0 || f.rtype[j] > 3)
+            return fail(PYRO_E_FORMAT, "reaction " + std::to_string(j) + ": unknown class");
+        if (f.rev[j] != 0 && f.rev[j] != 1)
+            return fail(PYRO_E_FORMAT, "reaction " + std::to_string(j) + ": bad reversible flag");
+        n_tb += f.rtype[j] == 1;
+        n_fo += f.rtype[j] >= 2;
+    }
+    if (n_tb != f.n_tb || n_fo != f.n_fo)
+        return fail(PYRO_E_FORMAT, "reaction classes do not match the header counts");
+    auto check_csr = [&](const std::vector<int32_t>& ptr, const std::vector<int32_t>& sp,
+                         const std::vector<int32_t>& nu, const char* side) -> int {
+        if (ptr[0] != 0 || size_t(ptr[f.R]) != sp.size())
+            return fail(PYRO_E_FORMAT, std::string(side) + " list pointers are inconsistent");
+        for (uint32_t j = 0; j < f.R; ++j) {
+            if (ptr[j + 1] < ptr[j])
+                return fail(PYRO_E_FORMAT, std::string(side) + " list pointers decrease");
+            for (int32_t q = ptr[j]; q < ptr[j + 1]; ++q) {
+                if (sp[q] < 0 || uint32_t(sp[q]) >= f.S)
+                    return fail(PYRO_E_FORMAT, std::string(side) + " species index out of range");
+                if (nu[q] < 1 || nu[q] > 16)
+                    return fail(PYRO_E_FORMAT, std::string(side) + " stoichiometric coefficient out of range");
+            }
+        }
+        return PYRO_OK;
+    };
+    if (int rc = check_csr(f.rp, f.rs, f.rn, "reactant")) return rc;
+    if (int rc = check_csr(f.pp, f.ps, f.pn, "product")) return rc;
+    for (uint32_t i = 0, j = 0; j < f.R; ++j) {
+        if (f.rtype[j] >= 2) {
+            if (f.fo[i] != int32_t(j))
+                return fail(PYRO_E_FORMAT, "falloff reaction list does not match the classes");
+            ++i;
+        }
+    }
+    for (uint32_t i = 0; i < f.n_fo; ++i) {
+        const double* t = &f.troe[4 * i];
+        if (f.rtype[f.fo[i]] == 3 && !(t[1] > 0 && t[2] > 0 && t[3] >= 0))
+            return fail(PYRO_E_FORMAT, "Troe temperatures must be positive");
+    }
+    return PYRO_OK;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+}  // namespace
+
+int load_mechanism(const char* path, pyro_mech** out) {
+    std::ifstream in(path, std::ios::binary);
+    if (!in) return fail(PYRO_E_IO, std::string("cannot open ") + path);
+    std::vector<uint8_t> blob((std::istreambuf_iterator<char>(in)), std::istreambuf_iterator<char>());
+    Parsed f;
+    if (int rc = parse(blob, f)) return rc;
+    const int S = int(f.S), R = int(f.R), n_fo = int(f.n_fo), n_pd = int(f.n_tb + f.n_fo);
+
+    // ---- reactions: slots, stoichiometry, classes
+    std::vector<std::vector<int>> reac(R), prod(R);
+    std::vector<int> dnu(R, 0);
+    for (int j = 0; j < R; ++j) {
+        for (int q = f.rp[j]; q < f.rp[j + 1]; ++q)
+            for (int c = 0; c < f.rn[q]; ++c) reac[j].push_back(f.rs[q]);
+        for (int q = f.pp[j]; q < f.pp[j + 1]; ++q)
+            for (int c = 0; c < f.pn[q]; ++c) prod[j].push_back(f.ps[q]);
+        if (reac[j].empty() || prod[j].empty())
+            return fail(PYRO_E_FORMAT, "reaction " + std::to_string(j) + " has an empty side");
+        if (reac[j].size() > size_t(kMaxSide) || prod[j].size() > size_t(kMaxSide))
+            return fail(PYRO_E_UNSUPPORTED, "reaction " + std::to_string(j) +
+                        " has more than 3 molecules on one side");
+        dnu[j] = int(prod[j].size()) - int(reac[j].size());
+    }
+    std::vector<int> pd_row(R, -1), fo_idx(R, -1);
+    for (int j = 0, i = 0, fi = 0; j < R; ++j) {
+        if (f.rtype[j] >= 1) pd_row[j] = i++;
+        if (f.rtype[j] >= 2) fo_idx[j] = fi++;
+    }
+    // net coefficients per (species, reaction)
+    std::vector<std::vector<std::pair<int, double>>> by_species(S);
+    int nnz_f = 0, nnz_r = 0, nnz_net = 0;
+    for (int j = 0; j < R; ++j) {
+        std::vector<double> nu(S, 0.0), nf(S, 0.0), nr(S, 0.0);
+        for (int k : prod[j]) nu[k] += 1, nr[k] += 1;
+        for (int k : reac[j]) nu[k] -= 1, nf[k] += 1;
+        for (int k = 0; k < S; ++k) {
+            if (nu[k] != 0) by_species[k].push_back({j, nu[k]});
+            nnz_f += nf[k] != 0;
+            nnz_r += nr[k] != 0;
+            nnz_net += nu[k] != 0;
+        }
+    }
+
+    // ---- LDS fit of the 64-cell tile
+    pyro_mech* m = new pyro_mech();
+    m->S = S; m->R = R; m->E = int(f.E); m->n_tb = int(f.n_tb); m->n_fo = n_fo;
+    m->nnz_f = nnz_f; m->nnz_r = nnz_r; m->nnz_net = nnz_net;
+    m->W = f.W;
+    m->params.resize(size_t(R + n_fo) * 3);
+    std::copy(f.arrh.begin(), f.arrh.end(), m->params.begin());
+    std::copy(f.low.begin(), f.low.end(), m->params.begin() + size_t(R) * 3);
+    if (production_rates_lds_bytes(m) > 160 * 1024) {
+        delete m;
+        return fail(PYRO_E_UNSUPPORTED, "mechanism too large for the 64-cell LDS tile");
+    }
+
+    // ---- species ownership: balance the gathering work over the waves
+    std::vector<int> order(S);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        return by_species[a].size() > by_species[b].size();
+    });
+    std::vector<std::vector<int>> own(kWaves);
+    std::vector<double> load(kWaves, 0.0);
+    for (int k : order) {
+        int best = -1;
+        for (int w = 0; w < kWaves; ++w)
+            if (int(own[w].size()) < kMaxOwn && (best < 0 || load[w] < load[best])) best = w;
+        if (best < 0) {
+            delete m;
+            return fail(PYRO_E_UNSUPPORTED, "too many species for one workgroup");
+        }
+        own[best].push_back(k);
+        load[best] += 2.0 + double(by_species[k].size());
+    }
+    for (auto& o : own) std::sort(o.begin(), o.end());
+    m->max_own = 0;
+    for (auto& o : own) m->max_own = std::max<int>(m->max_own, int(o.size()));
+
+    // ---- reaction schedule: chunks of kChunk, balanced over the waves
+    auto cost = [&](int j) {
+        double c = 1.0 + (f.rev[j] ? 0.5 : 0.0);
+        if (f.rtype[j] >= 1) c += S / 24.0;
+        if (f.rtype[j] == 2) c += 1.5;
+        if (f.rtype[j] == 3) c += 6.0;
+        return c;
+    };
+    std::vector<int> rorder(R);
+    std::iota(rorder.begin(), rorder.end(), 0);
+    std::stable_sort(rorder.begin(), rorder.end(), [&](int a, int b) { return cost(a) > cost(b); });
+    const int n_chunks = (R + kChunk - 1) / kChunk;
+    std::vector<RxnRec> recs(size_t(std::max(n_chunks, 1)) * kChunk);
+    for (auto& r : recs) {
+        std::memset(&r, 0, sizeof(r));
+        r.cls = kNoReaction;
+    }
+    std::vector<int> slot_of(R, -1), chunk_of(R, -1);
+    const int cg_stride = kTile * 16;  // bytes per species row of the C/G tile
+    for (int c = 0; c < n_chunks; ++c) {
+        std::vector<double> wl(kWaves, 0.0);
+        std::vector<int> used(kWaves, 0);
+        for (int t = c * kChunk; t < std::min(R, (c + 1) * kChunk); ++t) {
+            const int j = rorder[t];
+            int best = -1;
+            for (int w = 0; w < kWaves; ++w)
+                if (used[w] < kRxnPerWave && (best < 0 || wl[w] < wl[best])) best = w;
+            const int slot = best * kRxnPerWave + used[best]++;
+            wl[best] += cost(j);
+            slot_of[j] = slot;
+            chunk_of[j] = c;
+            RxnRec& r = recs[size_t(c) * kChunk + slot];
+            r.cls = f.rtype[j];
+            r.rev = f.rev[j];
+            r.nr = int(reac[j].size());
+            r.np = int(prod[j].size());
+            for (int s = 0; s < kMaxSide; ++s) {
+                r.r[s] = s < r.nr ? reac[j][s] * cg_stride : 0;
+                r.p[s] = s < r.np ? prod[j][s] * cg_stride : 0;
+            }
+            r.dnu = dnu[j];
+            r.prow = j;
+            r.pd = pd_row[j];
+            r.fo = fo_idx[j];
+            r.qoff = slot * kTile * 8;
+        }
+    }
+    // ---- gathering lists: (chunk, wave, owned species) -> (slot, nu)
+    std::vector<int32_t> gptr;
+    std::vector<GatherEntry> gent;
+    gptr.reserve(size_t(std::max(n_chunks, 1)) * kWaves * (kMaxOwn + 1));
+    for (int c = 0; c < std::max(n_chunks, 1); ++c)
+        for (int w = 0; w < kWaves; ++w)
+            for (int i = 0; i <= kMaxOwn; ++i) {
+                gptr.push_back(int32_t(gent.size()));
+                if (i == kMaxOwn || i >= int(own[w].size())) continue;
+                for (auto& e : by_species[own[w][i]])
+                    if (chunk_of[e.first] == c) {
+                        GatherEntry g{};
+                        g.qoff = slot_of[e.first] * kTile * 8;
+                        g.nu = e.second;
+                        gent.push_back(g);
+                    }
+            }
+    // gptr holds, per (c, w), kMaxOwn + 1 boundaries; entry i of the owned
+    // list spans [gptr[base + i], gptr[base + i + 1]).
+    if (gent.empty()) gent.push_back(GatherEntry{});
+
+    // ---- species tables
+    std::vector<SpeciesRec> sp(S);
+    std::vector<NewtonSpecies> ns(S);
+    std::vector<double> tmid_groups;
+    for (int k = 0; k < S; ++k) {
+        const double* a = &f.nasa[size_t(k) * 14];
+        for (int r = 0; r < 2; ++r) {
+            const double* c = a + 7 * r;
+            double* g = r == 0 ? sp[k].lo : sp[k].hi;
+            g[0] = c[0];
+            g[1] = -c[1] / 2.0;
+            g[2] = -c[2] / 6.0;
+            g[3] = -c[3] / 12.0;
+            g[4] = -c[4] / 20.0;
+            g[5] = c[5];
+            g[6] = -c[6];
+            double* nn = r == 0 ? ns[k].lo : ns[k].hi;
+            for (int q = 0; q < 6; ++q) nn[q] = c[q];
+        }
+        sp[k].t_mid = f.trange[3 * k + 1];
+        sp[k].inv_w = 1.0 / f.W[k];
+        ns[k].inv_w = 1.0 / f.W[k];
+        auto it = std::find(tmid_groups.begin(), tmid_groups.end(), sp[k].t_mid);
+        if (it == tmid_groups.end()) {
+            if (int(tmid_groups.size()) == kMaxTmidGroups) {
+                delete m;
+                return fail(PYRO_E_UNSUPPORTED, "more than 4 distinct NASA7 T_mid values");
+            }
+            tmid_groups.push_back(sp[k].t_mid);
+            it = tmid_groups.end() - 1;
+        }
+        ns[k].group = int(it - tmid_groups.begin());
+    }
+    std::vector<FalloffRec> fr(std::max(n_fo, 1));
+    for (auto& x : fr) std::memset(&x, 0, sizeof(x));
+    for (int i = 0; i < n_fo; ++i) {
+        const double* t = &f.troe[4 * i];
+        fr[i].troe = f.rtype[f.fo[i]] == 3;
+        fr[i].alpha = t[0];
+        fr[i].a3 = fr[i].troe ? -1.0 / t[1] : 0.0;
+        fr[i].a1 = fr[i].troe ? -1.0 / t[2] : 0.0;
+        fr[i].a2 = -t[3];
+    }
+    const int s_pad = (S + 7) / 8 * 8;
+    std::vector<double> eff(size_t(std::max(n_pd, 1)) * s_pad, 0.0);
+    for (int i = 0; i < n_pd; ++i)
+        for (int k = 0; k < S; ++k) eff[size_t(i) * s_pad + k] = f.eff[size_t(i) * S + k];
+    std::vector<int32_t> own_tab(kWaves * kMaxOwn, -1), n_own(kWaves);
+    for (int w = 0; w < kWaves; ++w) {
+        n_own[w] = int(own[w].size());
+        for (size_t i = 0; i < own[w].size(); ++i) own_tab[w * kMaxOwn + i] = own[w][i];
+    }
+    std::vector<double> params = m->params;
+    if (params.empty()) params.push_back(0.0);
+
+    // ---- one device allocation holding every table
+    struct Part { const void* src; size_t bytes; size_t off; };
+    std::vector<Part> parts = {
+        {sp.data(), sp.size() * sizeof(SpeciesRec), 0},
+        {recs.data(), recs.size() * sizeof(RxnRec), 0},
+        {fr.data(), fr.size() * sizeof(FalloffRec), 0},
+        {eff.data(), eff.size() * sizeof(double), 0},
+        {params.data(), params.size() * sizeof(double), 0},
+        {own_tab.data(), own_tab.size() * sizeof(int32_t), 0},
+        {n_own.data(), n_own.size() * sizeof(int32_t), 0},
+        {gptr.data(), gptr.size() * sizeof(int32_t), 0},
+        {gent.data(), gent.size() * sizeof(GatherEntry), 0},
+        {ns.data(), ns.size() * sizeof(NewtonSpecies), 0},
+        {f.W.data(), f.W.size() * sizeof(double), 0},
+    };
+    size_t total = 0;
+    for (auto& p : parts) {
+        p.off = total;
+        total = align256(total + p.bytes);
+    }
+    std::vector<uint8_t> host(total, 0);
+    for (auto& p : parts) std::memcpy(host.data() + p.off, p.src, p.bytes);
+
+    hipError_t err = hipGetDevice(&m->device);
+    if (err != hipSuccess) {
+        delete m;
+        return hip_fail(err, "hipGetDevice");
+    }
+    err = hipMalloc(&m->blob, total);
+    if (err != hipSuccess) {
+        delete m;
+        return err == hipErrorOutOfMemory ? fail(PYRO_E_NOMEM, "hipMalloc of the mechanism tables failed")
+                                          : hip_fail(err, "hipMalloc");
+    }
+    m->blob_bytes = total;
+    err = hipMemcpy(m->blob, host.data(), total, hipMemcpyHostToDevice);
+    if (err != hipSuccess) {
+        (void)hipFree(m->blob);
+        delete m;
+        return hip_fail(err, "hipMemcpy of the mechanism tables");
+    }
+    const uint8_t* base = static_cast<const uint8_t*>(m->blob);
+    DevMech& d = m->dev;
+    d.S = S; d.R = R; d.n_pd = n_pd; d.n_fo = n_fo;
+    d.n_chunks = n_chunks;
+    d.s_pad = s_pad;
+    d.n_groups = int(tmid_groups.size());
+    for (int g = 0; g < kMaxTmidGroups; ++g)
+        d.t_mid_group[g] = g < d.n_groups ? tmid_groups[g] : 0.0;
+    d.species = reinterpret_cast<const SpeciesRec*>(base + parts[0].off);
+    d.rxn = reinterpret_cast<const RxnRec*>(base + parts[1].off);
+    d.falloff = reinterpret_cast<const FalloffRec*>(base + parts[2].off);
+    d.eff = reinterpret_cast<const double*>(base + parts[3].off);
+    d.params = reinterpret_cast<const double*>(base + parts[4].off);
+    d.own = reinterpret_cast<const int32_t*>(base + parts[5].off);
+    d.n_own = reinterpret_cast<const int32_t*>(base + parts[6].off);
+    d.gptr = reinterpret_cast<const int32_t*>(base + parts[7].off);
+    d.gent = reinterpret_cast<const GatherEntry*>(base + parts[8].off);
+    d.newton = reinterpret_cast<const NewtonSpecies*>(base + parts[9].off);
+    d.w = reinterpret_cast<const double*>(base + parts[10].off);
+    err = prepare_production_rates(m);
+    if (err != hipSuccess) {
+        (void)hipFree(m->blob);
+        delete m;
+        return hip_fail(err, "hipFuncSetAttribute");
+    }
+    *out = m;
+    return PYRO_OK;
+}
+
+}  // namespace pyro

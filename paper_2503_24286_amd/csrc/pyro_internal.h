@@ -1,0 +1,160 @@
+// Internal declarations of libpyro: device tables of a loaded mechanism and
+// the kernel launchers.  Not part of the public ABI (include/pyro.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/pyro.h"
+
+namespace pyro {
+
+// Universal gas constant (J mol^-1 K^-1) and the 1 atm reference pressure of
+// the equilibrium constants (Appendix A.1, eq. equil_constants).
+constexpr double kGasConstant = 8.314462618;
+constexpr double kOneAtm = 101325.0;
+
+// Cells per tile of the production-rate kernel (one cell per lane of a
+// 64-wide wavefront) and waves per workgroup.
+constexpr int kTile = 64;
+constexpr int kWaves = 4;
+// Reactions each wave evaluates per chunk; a chunk's rates of progress are
+// parked in LDS before the species that own them gather their sums.
+constexpr int kRxnPerWave = 4;
+constexpr int kChunk = kWaves * kRxnPerWave;
+// Max species a wave owns (accumulates) in the production-rate kernel.
+constexpr int kMaxOwn = 64;
+// Max molecules per reaction side.
+constexpr int kMaxSide = 3;
+// Max distinct T_mid values among the species (Newton kernel groups).
+constexpr int kMaxTmidGroups = 4;
+
+// Reaction classes.
+enum : int32_t { kElementary = 0, kThirdBody = 1, kLindemann = 2, kTroe = 3,
+                 kNoReaction = -1 };
+
+// One reaction as the production-rate kernel reads it: 64 bytes, read with a
+// single scalar load because every lane of a wave handles the same reaction.
+struct RxnRec {
+    int32_t cls;          // class, or kNoReaction for an empty slot
+    int32_t rev;          // 1 if reversible
+    int32_t nr, np;       // molecules on each side (1..3)
+    int32_t r[kMaxSide];  // byte offsets of the reactant slots in the C/G tile
+    int32_t p[kMaxSide];  // byte offsets of the product slots
+    int32_t dnu;          // sum of the net stoichiometric coefficients
+    int32_t prow;         // row of the Arrhenius triple (the reaction index)
+    int32_t pd;           // row of the efficiency table, -1 if none
+    int32_t fo;           // falloff index, -1 if none
+    int32_t qoff;         // byte offset of the rate-of-progress slot in a chunk
+    int32_t pad;
+};
+static_assert(sizeof(RxnRec) == 64, "RxnRec must be 64 bytes");
+
+// Species data of the species phase: g/RT coefficients for both NASA7
+// ranges, with g/RT = c0 (1 - ln T) + c1 T + c2 T^2 + c3 T^3 + c4 T^4
+// + c5 / T + c6, then T_mid and 1/W.
+struct SpeciesRec {
+    double lo[7];
+    double hi[7];
+    double t_mid;
+    double inv_w;
+};
+static_assert(sizeof(SpeciesRec) == 128, "SpeciesRec must be 128 bytes");
+
+// Troe data per falloff reaction: F_cent = (1-alpha) exp(T a3) + alpha
+// exp(T a1) + exp(a2 / T) with a3 = -1/T***, a1 = -1/T*, a2 = -T**.
+struct FalloffRec {
+    double alpha, a3, a1, a2;
+    int32_t troe;
+    int32_t pad[7];
+};
+static_assert(sizeof(FalloffRec) == 64, "FalloffRec must be 64 bytes");
+
+// Gathering entry: chunk slot of a rate of progress and its coefficient.
+struct GatherEntry {
+    int32_t qoff;         // byte offset of the slot in the chunk buffer
+    int32_t pad;
+    double nu;
+};
+
+// Newton-kernel data: NASA7 coefficients a1..a6 of each range and 1/W.
+struct NewtonSpecies {
+    double lo[6];
+    double hi[6];
+    double inv_w;
+    int32_t group;
+    int32_t pad;
+    double pad2[2];
+};
+static_assert(sizeof(NewtonSpecies) == 128, "NewtonSpecies must be 128 bytes");
+
+// Device-side view of a mechanism, passed to kernels by value.
+struct DevMech {
+    int32_t S, R, n_pd, n_fo;
+    int32_t n_chunks;
+    int32_t s_pad;                       // S rounded up to a multiple of 8
+    int32_t n_groups;
+    int32_t pad;
+    double t_mid_group[kMaxTmidGroups];
+    const SpeciesRec* species;           // [S]
+    const RxnRec* rxn;                   // [n_chunks][kWaves][kRxnPerWave]
+    const FalloffRec* falloff;           // [n_fo]
+    const double* eff;                   // [n_pd][s_pad]
+    const double* params;                // [R + n_fo][3] default triples
+    const int32_t* own;                  // [kWaves][kMaxOwn] species owned
+    const int32_t* n_own;                // [kWaves]
+    const int32_t* gptr;                 // [n_chunks][kWaves][kMaxOwn + 1]
+    const GatherEntry* gent;             // gathering entries
+    const NewtonSpecies* newton;         // [S]
+    const double* w;                     // [S] molar masses
+};
+
+}  // namespace pyro
+
+struct pyro_mech {
+    int device = 0;
+    int S = 0, R = 0, E = 0, n_tb = 0, n_fo = 0;
+    int nnz_f = 0, nnz_r = 0, nnz_net = 0;
+    int max_own = 0;
+    std::vector<double> W;               // host copy
+    std::vector<double> params;          // host copy of the default triples
+    pyro::DevMech dev{};
+    void* blob = nullptr;                // one device allocation for all tables
+    size_t blob_bytes = 0;
+};
+
+namespace pyro {
+
+// Thread-local error message used by pyro_last_error().
+void set_error(const std::string& msg);
+void clear_error();
+int fail(int code, const std::string& msg);
+int hip_fail(hipError_t err, const char* what);
+
+// Parses and validates a .pyromech file, builds the tables and uploads them.
+int load_mechanism(const char* path, pyro_mech** out);
+
+// Launchers (arguments already validated).
+hipError_t launch_production_rates(const pyro_mech* m, int64_t n, int64_t ld,
+                                   int dtype, const void* rho, const void* T,
+                                   const void* Y, void* wdot,
+                                   const double* params, hipStream_t stream);
+hipError_t launch_temperature(const pyro_mech* m, int64_t n, int64_t ld,
+                              const double* e, const double* Y,
+                              const double* T_guess, double T_guess_value,
+                              double* T_out, int32_t* status, int max_iter,
+                              double rtol, hipStream_t stream);
+hipError_t launch_eos(const pyro_mech* m, int64_t n, int64_t ld, int mode,
+                      const double* a, const double* T, const double* Y,
+                      double* out, hipStream_t stream);
+hipError_t launch_internal_energy(const pyro_mech* m, int64_t n, int64_t ld,
+                                  const double* T, const double* Y,
+                                  double* e_out, hipStream_t stream);
+// LDS bytes the production-rate kernel needs for this mechanism.
+size_t production_rates_lds_bytes(const pyro_mech* m);
+hipError_t prepare_production_rates(const pyro_mech* m);
+
+}  // namespace pyro

@@ -1,0 +1,92 @@
+"""Parity of the Newton temperature inversion and the EOS/energy helpers with
+the oracle, through the C ABI."""
+
+import numpy as np
+import pytest
+
+import mechs
+from gpu_util import announce, states, to_dev, torch_cuda
+from oracle import eos, newton, thermo
+from pyro_synth.states import draw_guess_factors
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lib_mechs():
+    torch = torch_cuda()
+    import paper_2503_24286_amd as pyro
+    out = {c: pyro.Mechanism(mechs.config_path(c)) for c in (0, 1)}
+    yield torch, pyro, out
+    for m in out.values():
+        m.close()
+
+
+@pytest.mark.parametrize("cfg,n", [(0, 4096), (1, 3000)])
+@pytest.mark.parametrize("guess", ["fixed", "per-cell"])
+def test_newton_matches_oracle(lib_mechs, cfg, n, guess):
+    torch, pyro, gms = lib_mechs
+    m = mechs.load_config(cfg)
+    T, p, Y, rho = states(cfg, n, m.S)
+    e = thermo.mixture_internal_energy(m, T, Y)
+    Tg = 1200.0 if guess == "fixed" else T * draw_guess_factors(cfg, n)
+    T_ref, st_ref = newton.temperature(m, e, Y, Tg)
+    announce(f"newton cfg{cfg} n={n} guess={guess}")
+    e_d, Y_d = to_dev(torch, e, Y)
+    tg = Tg if guess == "fixed" else to_dev(torch, Tg)[0]
+    T_gpu, st = pyro.temperature(gms[cfg], e_d, Y_d, T_guess=tg)
+    torch.cuda.synchronize()
+    T_gpu = T_gpu.cpu().numpy()
+    st = st.cpu().numpy()
+    assert np.all(st > 0) and np.all(st_ref > 0)
+    np.testing.assert_allclose(T_gpu, T_ref, rtol=1e-12, atol=0)
+    np.testing.assert_allclose(T_gpu, T, rtol=1e-12, atol=0)
+    # iteration counts agree up to the last, rounding-decided update
+    assert np.all(np.abs(st - st_ref) <= 1)
+
+
+def test_newton_iteration_limit(lib_mechs):
+    torch, pyro, gms = lib_mechs
+    m = mechs.load_config(1)
+    T, p, Y, rho = states(1, 300, m.S)
+    e = thermo.mixture_internal_energy(m, T, Y)
+    T1, st1 = newton.temperature(m, e, Y, 1200.0, max_iter=1)
+    announce("newton max_iter=1")
+    e_d, Y_d = to_dev(torch, e, Y)
+    T_gpu, st = pyro.temperature(gms[1], e_d, Y_d, T_guess=1200.0, max_iter=1)
+    torch.cuda.synchronize()
+    assert np.all(st.cpu().numpy() == st1)
+    np.testing.assert_allclose(T_gpu.cpu().numpy(), T1, rtol=1e-12)
+
+
+@pytest.mark.parametrize("n", [1, 63, 65, 257])
+def test_newton_ragged_and_padded(lib_mechs, n):
+    torch, pyro, gms = lib_mechs
+    m = mechs.load_config(1)
+    T, p, Y, rho = states(1, n, m.S, first=300)
+    e = thermo.mixture_internal_energy(m, T, Y)
+    announce(f"newton ragged n={n}")
+    Yb = torch.full((m.S, n + 5), float("nan"), dtype=torch.float64, device="cuda")
+    Yb[:, :n] = torch.from_numpy(Y).cuda()
+    (e_d,) = to_dev(torch, e)
+    T_gpu, st = pyro.temperature(gms[1], e_d, Yb[:, :n], T_guess=1500.0)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(T_gpu.cpu().numpy(), T, rtol=1e-12)
+
+
+def test_eos_and_energy_helpers(lib_mechs):
+    torch, pyro, gms = lib_mechs
+    m = mechs.load_config(1)
+    T, p, Y, rho = states(1, 2000, m.S, first=40000)
+    announce("eos helpers")
+    p_d, T_d, Y_d, rho_d = to_dev(torch, p, T, Y, rho)
+    r = pyro.density(gms[1], p_d, T_d, Y_d)
+    pp = pyro.pressure(gms[1], rho_d, T_d, Y_d)
+    e = pyro.internal_energy(gms[1], T_d, Y_d)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(r.cpu().numpy(), eos.density(m, p, T, Y), rtol=1e-14)
+    np.testing.assert_allclose(pp.cpu().numpy(), eos.pressure(m, rho, T, Y), rtol=1e-14)
+    e_ref = thermo.mixture_internal_energy(m, T, Y)
+    # e is a sum of terms of both signs: compare against their magnitude
+    scale = np.abs(Y * thermo.species_internal_energy(m, T)).sum(axis=0)
+    assert np.all(np.abs(e.cpu().numpy() - e_ref) <= 1e-13 * scale)

@@ -1,0 +1,137 @@
+"""Parity of the HIP production-rate kernel with the oracle, through the C ABI."""
+
+import numpy as np
+import pytest
+
+import mechs
+from gpu_util import announce, states, to_dev, torch_cuda
+from parity import assert_wdot_parity
+from oracle import kinetics
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lib_mechs():
+    torch = torch_cuda()
+    import paper_2503_24286_amd as pyro
+    out = {c: pyro.Mechanism(mechs.config_path(c)) for c in (0, 1)}
+    yield torch, pyro, out
+    for m in out.values():
+        m.close()
+
+
+def _run(torch, pyro, gm, rho, T, Y, params=None):
+    r, t, y = to_dev(torch, rho, T, Y)
+    p = None if params is None else to_dev(torch, params)[0]
+    w = pyro.production_rates(gm, r, t, y, params=p)
+    torch.cuda.synchronize()
+    return w.cpu().numpy()
+
+
+@pytest.mark.parametrize("cfg,n", [(0, 4096), (1, 1000), (1, 4096 + 37)])
+def test_wdot_matches_oracle(lib_mechs, cfg, n):
+    torch, pyro, gms = lib_mechs
+    m = mechs.load_config(cfg)
+    T, p, Y, rho = states(cfg, n, m.S)
+    announce(f"wdot cfg{cfg} n={n}")
+    w = _run(torch, pyro, gms[cfg], rho, T, Y)
+    r = assert_wdot_parity(m, rho, T, Y, w)
+    announce(f"  max scaled {r['scaled'].max():.2e}")
+
+
+@pytest.mark.parametrize("n", [1, 2, 63, 64, 65, 127, 129, 200])
+def test_wdot_ragged_sizes_and_padded_rows(lib_mechs, n):
+    """Partial tiles and a row stride ld > n: padding must neither be read
+    into results nor written."""
+    torch, pyro, gms = lib_mechs
+    m = mechs.load_config(1)
+    T, p, Y, rho = states(1, n, m.S, first=5000)
+    ld = n + 29
+    announce(f"wdot ragged n={n} ld={ld}")
+    Yb = torch.full((m.S, ld), float("nan"), dtype=torch.float64, device="cuda")
+    Yb[:, :n] = torch.from_numpy(Y).cuda()
+    out = torch.full((m.S, ld), -7.0, dtype=torch.float64, device="cuda")
+    r, t = to_dev(torch, rho, T)
+    pyro.production_rates(gms[1], r, t, Yb[:, :n], out=out[:, :n])
+    torch.cuda.synchronize()
+    o = out.cpu().numpy()
+    assert np.all(o[:, n:] == -7.0)
+    assert_wdot_parity(m, rho, T, Y, o[:, :n])
+
+
+def test_wdot_tiled_states_identical(lib_mechs):
+    """The same state repeated over a grid gives the same result in every
+    cell (the paper's multi-dimensional input example, Sec. 4.1)."""
+    torch, pyro, gms = lib_mechs
+    m = mechs.load_config(1)
+    T, p, Y, rho = states(1, 3, m.S, first=77)
+    reps = 300
+    announce("wdot tiled states")
+    w = _run(torch, pyro, gms[1], np.tile(rho, reps), np.tile(T, reps), np.tile(Y, reps))
+    w = w.reshape(m.S, reps, 3)
+    assert np.all(w == w[:, :1, :])
+    assert_wdot_parity(m, rho, T, Y, w[:, 0, :])
+
+
+def test_wdot_zero_cells_is_noop(lib_mechs):
+    torch, pyro, gms = lib_mechs
+    S = gms[1].n_species
+    announce("wdot n=0")
+    e = torch.empty(0, dtype=torch.float64, device="cuda")
+    w = pyro.production_rates(gms[1], e, e, torch.empty((S, 0), dtype=torch.float64, device="cuda"))
+    torch.cuda.synchronize()
+    assert w.shape == (S, 0)
+
+
+def test_wdot_degenerate_states(lib_mechs):
+    """Zero and negative mass fractions, a single-species mixture, and the
+    ends of the NASA7 ranges (T at T_mid exactly and just above)."""
+    torch, pyro, gms = lib_mechs
+    m = mechs.load_config(1)
+    T, p, Y, rho = states(1, 256, m.S, first=9000)
+    Y[:, :64] = 0.0
+    Y[5, :64] = 1.0                       # pure species 5
+    Y[3, 64:128] = -1e-3                  # negative mass fraction counts as zero
+    Y[:, 128:192] *= 0.5                  # sum(Y) = 1/2
+    T[192:200] = m.T_mid[0]
+    T[200:208] = np.nextafter(m.T_mid[0], 4000.0)
+    announce("wdot degenerate states")
+    w = _run(torch, pyro, gms[1], rho, T, Y)
+    assert_wdot_parity(m, rho, T, Y, w)
+    inert = np.nonzero(np.abs(m.nu).sum(axis=1) == 0)[0]
+    assert np.all(w[inert] == 0.0)
+
+
+def test_wdot_parameter_override(lib_mechs):
+    torch, pyro, gms = lib_mechs
+    m = mechs.load_config(1)
+    T, p, Y, rho = states(1, 500, m.S, first=123)
+    P = m.parameters().copy()
+    rng = np.random.default_rng(8)
+    P[:, 0] += rng.uniform(-1, 1, P.shape[0])
+    P[:, 1] += rng.uniform(-0.2, 0.2, P.shape[0])
+    P[:, 2] *= rng.uniform(0.8, 1.2, P.shape[0])
+    announce("wdot params override")
+    w = _run(torch, pyro, gms[1], rho, T, Y, params=P.reshape(-1))
+    assert_wdot_parity(m, rho, T, Y, w, params=P)
+    assert np.allclose(gms[1].arrhenius, m.parameters(), rtol=0, atol=0)
+
+
+def test_wdot_full_size_sampled(lib_mechs):
+    """The benchmark's workload: 2^22 cells of config 1 in one launch;
+    sampled cells are checked against the oracle one by one."""
+    torch, pyro, gms = lib_mechs
+    m = mechs.load_config(1)
+    n = 1 << 22
+    T, p, Y, rho = states(1, n, m.S)
+    announce(f"wdot full size n={n}")
+    r, t, y = to_dev(torch, rho, T, Y)
+    w = pyro.production_rates(gms[1], r, t, y)
+    torch.cuda.synchronize()
+    assert bool(torch.isfinite(w).all())
+    rng = np.random.default_rng(99)
+    idx = np.unique(np.concatenate([rng.integers(0, n, 2000), np.arange(64),
+                                    np.arange(n - 64, n)]))
+    ws = w[:, torch.from_numpy(idx).cuda()].cpu().numpy()
+    assert_wdot_parity(m, rho[idx], T[idx], Y[:, idx], ws)
