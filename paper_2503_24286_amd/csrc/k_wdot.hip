@@ -3,14 +3,14 @@
 // eq. rate_coeff, eq. equil_constants, eq. reaction_rates,
 // eq. production_rates).
 //
-// Mapping on CDNA4: one cell per lane, four wavefronts per workgroup, all
+// Mapping on CDNA4: one cell per lane, eight wavefronts per workgroup, all
 // lanes of a wave on the same species or reaction at the same time, so every
 // mechanism-table read is wave-uniform and goes through the scalar cache.
 //
 //  1. species phase: each wave computes, for the species it owns,
 //     C_k = rho max(Y_k, 0)/W_k and G_k = exp(g0_k/(R T)) and parks the pair
 //     in LDS (row k, 16 bytes per lane);
-//  2. reaction phase, in chunks of 16 reactions (4 per wave): the forward
+//  2. reaction phase, in chunks of 16 reactions (2 per wave): the forward
 //     coefficient k = exp(ln A + b ln T - Ea/(R T)), third-body and falloff
 //     corrections, and the rate of progress
 //         q = k prod_r C_r - k (R T/p0)^dnu prod_p (C_p G_p) / prod_r G_r,
@@ -34,14 +34,29 @@ __device__ inline double2 lds_cg(const unsigned char* lds, int off, int lane) {
     return *reinterpret_cast<const double2*>(lds + off + lane * 16);
 }
 
-// Reaction rate of progress of one reaction for the calling lane's cell.
+// 1/x from the hardware estimate refined by two Newton steps
+// r <- r + r (1 - x r); each step squares the relative error.
+__device__ inline double recip(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return r;
+}
+
+// ln k of the Arrhenius triple in row ``row`` of ``params``.
+__device__ inline double log_arrhenius(const double* __restrict__ params, int row, double lnT,
+                                       double invRT) {
+    const double* p = params + 3 * row;
+    return fma(-p[2], invRT, fma(p[1], lnT, p[0]));
+}
+
+// Rate of progress of one reaction for the calling lane's cell, given its
+// Arrhenius coefficient kf.
 __device__ inline double rate_of_progress(const DevMech& m, const RxnRec& r,
                                           const double* __restrict__ params,
-                                          const unsigned char* lds, int lane,
+                                          const unsigned char* lds, int lane, double kf,
                                           double Tc, double lnT, double invT,
                                           double invRT, double rtp, double irtp) {
-    const double* pr = params + 3 * r.prow;
-    double kf = exp(pr[0] + pr[1] * lnT - pr[2] * invRT);
     double M = 1.0;
     if (r.cls >= kThirdBody) {
         // [M] = sum_k eps_k C_k
@@ -55,8 +70,7 @@ __device__ inline double rate_of_progress(const DevMech& m, const RxnRec& r,
         M = acc;
     }
     if (r.cls >= kLindemann) {
-        const double* pl = params + 3 * (m.R + r.fo);
-        const double k0 = exp(pl[0] + pl[1] * lnT - pl[2] * invRT);
+        const double k0 = exp(log_arrhenius(params, m.R + r.fo, lnT, invRT));
         const double Pr = k0 * M / kf;
         double F = 1.0;
         if (r.cls == kTroe) {
@@ -103,7 +117,7 @@ __device__ inline double rate_of_progress(const DevMech& m, const RxnRec& r,
             for (int i = 0; i < r.dnu; ++i) pw *= rtp;
         else
             for (int i = 0; i < -r.dnu; ++i) pw *= irtp;
-        q -= kf * pw * cgp / gr;
+        q -= kf * pw * cgp * recip(gr);
     }
     if (r.cls == kThirdBody) q *= M;
     return q;
@@ -130,21 +144,28 @@ __global__ __launch_bounds__(kWaves * 64) void wdot_f64_kernel(
     const double irtp = 1.0 / rtp;
     const double omlnT = 1.0 - lnT;
 
-    // ---- species phase
+    // ---- species phase: all of this wave's mass-fraction loads first
     const int nown = m.n_own[w];
     const int32_t* own = m.own + w * kMaxOwn;
-    for (int i = 0; i < nown; ++i) {
-        const int k = own[i];
-        const SpeciesRec& s = m.species[k];
-        const double y = Y[size_t(k) * ld + c];
-        const double Ck = rc * fmax(y, 0.0) * s.inv_w;
-        const bool low = Tc <= s.t_mid;
-        double g[7];
+    double y[MAXOWN];
 #pragma unroll
-        for (int q = 0; q < 7; ++q) g[q] = low ? s.lo[q] : s.hi[q];
-        const double gRT = g[0] * omlnT + g[6] + g[5] * invT +
-                           Tc * (g[1] + Tc * (g[2] + Tc * (g[3] + Tc * g[4])));
-        *reinterpret_cast<double2*>(lds + k * kCgStride + lane * 16) = make_double2(Ck, exp(gRT));
+    for (int i = 0; i < MAXOWN; ++i)
+        if (i < nown) y[i] = Y[size_t(own[i]) * ld + c];
+#pragma unroll
+    for (int i = 0; i < MAXOWN; ++i) {
+        if (i < nown) {
+            const int k = own[i];
+            const SpeciesRec& s = m.species[k];
+            const double Ck = rc * fmax(y[i], 0.0) * s.inv_w;
+            const bool low = Tc <= s.t_mid;
+            double g[7];
+#pragma unroll
+            for (int q = 0; q < 7; ++q) g[q] = low ? s.lo[q] : s.hi[q];
+            const double gRT = g[0] * omlnT + g[6] + g[5] * invT +
+                               Tc * (g[1] + Tc * (g[2] + Tc * (g[3] + Tc * g[4])));
+            *reinterpret_cast<double2*>(lds + k * kCgStride + lane * 16) =
+                make_double2(Ck, exp(gRT));
+        }
     }
     if (w == 0)
         for (int k = m.S; k < m.s_pad; ++k)
@@ -156,27 +177,40 @@ __global__ __launch_bounds__(kWaves * 64) void wdot_f64_kernel(
 #pragma unroll
     for (int i = 0; i < MAXOWN; ++i) acc[i] = 0.0;
     unsigned char* qbase = lds + size_t(m.s_pad) * kCgStride;
+    static_assert(kRxnPerWave == 2, "the reaction phase handles reactions in pairs");
     for (int ch = 0; ch < m.n_chunks; ++ch) {
         unsigned char* qb = qbase + (ch & 1) * kQBuf;
         const RxnRec* rb = m.rxn + (size_t(ch) * kWaves + w) * kRxnPerWave;
-        for (int t = 0; t < kRxnPerWave; ++t) {
-            const RxnRec r = rb[t];
-            if (r.cls == kNoReaction) continue;
-            const double q = rate_of_progress(m, r, params, lds, lane, Tc, lnT, invT, invRT, rtp, irtp);
-            *reinterpret_cast<double*>(qb + r.qoff + lane * 8) = q;
-        }
+        const RxnRec r0 = rb[0];
+        const RxnRec r1 = rb[1];
+        // both Arrhenius exponentials in one block, so they interleave
+        const double kf0 = exp(log_arrhenius(params, r0.prow, lnT, invRT));
+        const double kf1 = exp(log_arrhenius(params, r1.prow, lnT, invRT));
+        if (r0.cls != kNoReaction)
+            *reinterpret_cast<double*>(qb + r0.qoff + lane * 8) =
+                rate_of_progress(m, r0, params, lds, lane, kf0, Tc, lnT, invT, invRT, rtp, irtp);
+        if (r1.cls != kNoReaction)
+            *reinterpret_cast<double*>(qb + r1.qoff + lane * 8) =
+                rate_of_progress(m, r1, params, lds, lane, kf1, Tc, lnT, invT, invRT, rtp, irtp);
         __syncthreads();
         const int32_t* gp = m.gptr + (size_t(ch) * kWaves + w) * (kMaxOwn + 1);
 #pragma unroll
         for (int i = 0; i < MAXOWN; ++i) {
             if (i < nown) {
-                double a = acc[i];
+                double a = acc[i], b = 0.0;
+                int e = gp[i];
                 const int e1 = gp[i + 1];
-                for (int e = gp[i]; e < e1; ++e) {
-                    const GatherEntry g = m.gent[e];
-                    a = fma(g.nu, *reinterpret_cast<const double*>(qb + g.qoff + lane * 8), a);
+                for (; e + 1 < e1; e += 2) {
+                    const GatherEntry g0 = m.gent[e];
+                    const GatherEntry g1 = m.gent[e + 1];
+                    a = fma(g0.nu, *reinterpret_cast<const double*>(qb + g0.qoff + lane * 8), a);
+                    b = fma(g1.nu, *reinterpret_cast<const double*>(qb + g1.qoff + lane * 8), b);
                 }
-                acc[i] = a;
+                if (e < e1) {
+                    const GatherEntry g0 = m.gent[e];
+                    a = fma(g0.nu, *reinterpret_cast<const double*>(qb + g0.qoff + lane * 8), a);
+                }
+                acc[i] = a + b;
             }
         }
     }
@@ -208,8 +242,11 @@ size_t production_rates_lds_bytes(const pyro_mech* m) {
 
 hipError_t prepare_production_rates(const pyro_mech* m) {
     const int lds = int(production_rates_lds_bytes(m));
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&wdot_f64_kernel<16>),
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&wdot_f64_kernel<8>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute(reinterpret_cast<const void*>(&wdot_f64_kernel<16>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     if (e == hipSuccess)
         e = hipFuncSetAttribute(reinterpret_cast<const void*>(&wdot_f64_kernel<32>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, lds);
@@ -227,6 +264,7 @@ hipError_t launch_production_rates(const pyro_mech* m, int64_t n, int64_t ld, in
     const double* t = static_cast<const double*>(T);
     const double* y = static_cast<const double*>(Y);
     double* o = static_cast<double*>(wdot);
+    if (m->max_own <= 8) return launch_f64<8>(m, n, ld, r, t, y, o, params, stream);
     if (m->max_own <= 16) return launch_f64<16>(m, n, ld, r, t, y, o, params, stream);
     if (m->max_own <= 32) return launch_f64<32>(m, n, ld, r, t, y, o, params, stream);
     return launch_f64<64>(m, n, ld, r, t, y, o, params, stream);

@@ -20,10 +20,10 @@ constexpr double kOneAtm = 101325.0;
 // Cells per tile of the production-rate kernel (one cell per lane of a
 // 64-wide wavefront) and waves per workgroup.
 constexpr int kTile = 64;
-constexpr int kWaves = 4;
+constexpr int kWaves = 8;
 // Reactions each wave evaluates per chunk; a chunk's rates of progress are
 // parked in LDS before the species that own them gather their sums.
-constexpr int kRxnPerWave = 4;
+constexpr int kRxnPerWave = 2;
 constexpr int kChunk = kWaves * kRxnPerWave;
 // Max species a wave owns (accumulates) in the production-rate kernel.
 constexpr int kMaxOwn = 64;
