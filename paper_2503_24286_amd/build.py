@@ -24,8 +24,9 @@ def hipcc():
     raise RuntimeError("hipcc not found")
 
 
+INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-fvisibility=hidden", "-Wall",
-          "-Wno-unused-function"]
+          "-Wno-unused-function", f"-I{INCLUDE}"]
 # keep the compiler from emitting packed FP32 instructions
 DEVICE = ["-x", "hip", f"--offload-arch={ARCH}", "-Xclang", "-target-feature",
           "-Xclang", "-packed-fp32-ops", "-munsafe-fp-atomics"]

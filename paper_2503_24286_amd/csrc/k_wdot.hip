@@ -43,6 +43,12 @@ __device__ inline double recip(double x) {
     return r;
 }
 
+// g0/(R T) = c0 (1 - ln T) + c1 T + c2 T^2 + c3 T^3 + c4 T^4 + c5/T + c6.
+__device__ inline double gibbs_poly(const double* c, double T, double omlnT, double invT) {
+    return fma(c[0], omlnT, fma(c[5], invT, c[6])) +
+           T * fma(T, fma(T, fma(T, c[4], c[3]), c[2]), c[1]);
+}
+
 // ln k of the Arrhenius triple in row ``row`` of ``params``.
 __device__ inline double log_arrhenius(const double* __restrict__ params, int row, double lnT,
                                        double invRT) {
@@ -61,13 +67,18 @@ __device__ inline double rate_of_progress(const DevMech& m, const RxnRec& r,
     if (r.cls >= kThirdBody) {
         // [M] = sum_k eps_k C_k
         const double* e = m.eff + size_t(r.pd) * m.s_pad;
-        double acc = 0.0;
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
         for (int k = 0; k < m.s_pad; k += 8) {
-#pragma unroll
-            for (int u = 0; u < 8; ++u)
-                acc = fma(e[k + u], lds_cg(lds, (k + u) * kCgStride, lane).x, acc);
+            a0 = fma(e[k + 0], lds_cg(lds, (k + 0) * kCgStride, lane).x, a0);
+            a1 = fma(e[k + 1], lds_cg(lds, (k + 1) * kCgStride, lane).x, a1);
+            a2 = fma(e[k + 2], lds_cg(lds, (k + 2) * kCgStride, lane).x, a2);
+            a3 = fma(e[k + 3], lds_cg(lds, (k + 3) * kCgStride, lane).x, a3);
+            a0 = fma(e[k + 4], lds_cg(lds, (k + 4) * kCgStride, lane).x, a0);
+            a1 = fma(e[k + 5], lds_cg(lds, (k + 5) * kCgStride, lane).x, a1);
+            a2 = fma(e[k + 6], lds_cg(lds, (k + 6) * kCgStride, lane).x, a2);
+            a3 = fma(e[k + 7], lds_cg(lds, (k + 7) * kCgStride, lane).x, a3);
         }
-        M = acc;
+        M = (a0 + a1) + (a2 + a3);
     }
     if (r.cls >= kLindemann) {
         const double k0 = exp(log_arrhenius(params, m.R + r.fo, lnT, invRT));
@@ -157,12 +168,12 @@ __global__ __launch_bounds__(kWaves * 64) void wdot_f64_kernel(
             const int k = own[i];
             const SpeciesRec& s = m.species[k];
             const double Ck = rc * fmax(y[i], 0.0) * s.inv_w;
-            const bool low = Tc <= s.t_mid;
-            double g[7];
-#pragma unroll
-            for (int q = 0; q < 7; ++q) g[q] = low ? s.lo[q] : s.hi[q];
-            const double gRT = g[0] * omlnT + g[6] + g[5] * invT +
-                               Tc * (g[1] + Tc * (g[2] + Tc * (g[3] + Tc * g[4])));
+            // both ranges from scalar loads, then a per-lane select of the
+            // value (selecting the coefficient address would turn the
+            // uniform table reads into per-lane vector loads)
+            const double g_lo = gibbs_poly(s.lo, Tc, omlnT, invT);
+            const double g_hi = gibbs_poly(s.hi, Tc, omlnT, invT);
+            const double gRT = Tc <= s.t_mid ? g_lo : g_hi;
             *reinterpret_cast<double2*>(lds + k * kCgStride + lane * 16) =
                 make_double2(Ck, exp(gRT));
         }
@@ -193,22 +204,30 @@ __global__ __launch_bounds__(kWaves * 64) void wdot_f64_kernel(
             *reinterpret_cast<double*>(qb + r1.qoff + lane * 8) =
                 rate_of_progress(m, r1, params, lds, lane, kf1, Tc, lnT, invT, invRT, rtp, irtp);
         __syncthreads();
+        // gather: the boundaries of all owned species in one scalar load,
+        // then each species' entries in pairs
         const int32_t* gp = m.gptr + (size_t(ch) * kWaves + w) * (kMaxOwn + 1);
+        int32_t bound[MAXOWN + 1];
+#pragma unroll
+        for (int i = 0; i <= MAXOWN; ++i) bound[i] = gp[i];
 #pragma unroll
         for (int i = 0; i < MAXOWN; ++i) {
             if (i < nown) {
                 double a = acc[i], b = 0.0;
-                int e = gp[i];
-                const int e1 = gp[i + 1];
+                int e = bound[i];
+                const int e1 = bound[i + 1];
                 for (; e + 1 < e1; e += 2) {
                     const GatherEntry g0 = m.gent[e];
                     const GatherEntry g1 = m.gent[e + 1];
-                    a = fma(g0.nu, *reinterpret_cast<const double*>(qb + g0.qoff + lane * 8), a);
-                    b = fma(g1.nu, *reinterpret_cast<const double*>(qb + g1.qoff + lane * 8), b);
+                    const double q0 = *reinterpret_cast<const double*>(qb + (g0 & 0xffffu) + lane * 8);
+                    const double q1 = *reinterpret_cast<const double*>(qb + (g1 & 0xffffu) + lane * 8);
+                    a = fma(double(int16_t(g0 >> 16)), q0, a);
+                    b = fma(double(int16_t(g1 >> 16)), q1, b);
                 }
                 if (e < e1) {
                     const GatherEntry g0 = m.gent[e];
-                    a = fma(g0.nu, *reinterpret_cast<const double*>(qb + g0.qoff + lane * 8), a);
+                    a = fma(double(int16_t(g0 >> 16)),
+                            *reinterpret_cast<const double*>(qb + (g0 & 0xffffu) + lane * 8), a);
                 }
                 acc[i] = a + b;
             }

@@ -303,6 +303,8 @@ int load_mechanism(const char* path, pyro_mech** out) {
         }
     }
     // ---- gathering lists: (chunk, wave, owned species) -> (slot, nu)
+    // gptr holds, per (chunk, wave), kMaxOwn + 1 boundaries: the entries of
+    // owned species i span [gptr[base + i], gptr[base + i + 1]).
     std::vector<int32_t> gptr;
     std::vector<GatherEntry> gent;
     gptr.reserve(size_t(std::max(n_chunks, 1)) * kWaves * (kMaxOwn + 1));
@@ -313,15 +315,12 @@ int load_mechanism(const char* path, pyro_mech** out) {
                 if (i == kMaxOwn || i >= int(own[w].size())) continue;
                 for (auto& e : by_species[own[w][i]])
                     if (chunk_of[e.first] == c) {
-                        GatherEntry g{};
-                        g.qoff = slot_of[e.first] * kTile * 8;
-                        g.nu = e.second;
-                        gent.push_back(g);
+                        const uint32_t qoff = uint32_t(slot_of[e.first] * kTile * 8);
+                        const int nu = int(e.second);
+                        gent.push_back(qoff | (uint32_t(uint16_t(int16_t(nu))) << 16));
                     }
             }
-    // gptr holds, per (c, w), kMaxOwn + 1 boundaries; entry i of the owned
-    // list spans [gptr[base + i], gptr[base + i + 1]).
-    if (gent.empty()) gent.push_back(GatherEntry{});
+    gent.resize(gent.size() + 2, 0u);  // slack: the pairwise loop may read one past
 
     // ---- species tables
     std::vector<SpeciesRec> sp(S);

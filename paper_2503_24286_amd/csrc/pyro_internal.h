@@ -8,7 +8,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/pyro.h"
+#include "pyro.h"
 
 namespace pyro {
 
@@ -73,12 +73,10 @@ struct FalloffRec {
 };
 static_assert(sizeof(FalloffRec) == 64, "FalloffRec must be 64 bytes");
 
-// Gathering entry: chunk slot of a rate of progress and its coefficient.
-struct GatherEntry {
-    int32_t qoff;         // byte offset of the slot in the chunk buffer
-    int32_t pad;
-    double nu;
-};
+// Gathering entry: the byte offset of a rate-of-progress slot in its chunk
+// buffer (bits 0-15) and the net coefficient nu as a signed 16-bit integer
+// (bits 16-31).
+using GatherEntry = uint32_t;
 
 // Newton-kernel data: NASA7 coefficients a1..a6 of each range and 1/W.
 struct NewtonSpecies {
