@@ -8,17 +8,21 @@
 // mechanism-table read is wave-uniform and goes through the scalar cache.
 //
 //  1. species phase: each wave computes, for the species it owns,
-//     C_k = rho max(Y_k, 0)/W_k and G_k = exp(g0_k/(R T)) and parks the pair
-//     in LDS (row k, 16 bytes per lane);
-//  2. reaction phase, in chunks of 16 reactions (2 per wave): the forward
-//     coefficient k = exp(ln A + b ln T - Ea/(R T)), third-body and falloff
-//     corrections, and the rate of progress
+//     C_k = rho max(Y_k, 0)/W_k and G_k = exp(g0_k/(R T)) and parks them in
+//     LDS row k (C in the first 512 bytes, G in the second, so that both load
+//     with one ds_read2 and neither access has bank conflicts);
+//  2. third-body concentrations: each wave forms [M]_j = sum_k eps_jk C_k for
+//     the third-body and falloff reactions it evaluates, in one pass over the
+//     species, and keeps them in registers;
+//  3. reaction phase, in chunks of 16 reactions (2 per wave): the forward
+//     coefficient k = exp(ln A + b ln T - Ea/(R T)), falloff corrections, and
+//     the rate of progress
 //         q = k prod_r C_r - k (R T/p0)^dnu prod_p (C_p G_p) / prod_r G_r,
 //     which is eq. reaction_rates with 1/K = (R T/p0)^dnu prod G^nu; q goes to
 //     an LDS slot of the chunk (double buffered);
-//  3. after the chunk barrier, each wave adds nu_kj q_j into register
+//  4. after the chunk barrier, each wave adds nu_kj q_j into register
 //     accumulators of the species it owns, in a fixed order (deterministic);
-//  4. the owners write omega_k for the 64 cells (coalesced 512-byte rows).
+//  5. the owners write omega_k for the 64 cells (coalesced 512-byte rows).
 //
 // The equilibrium constant of every reaction thus costs products of S
 // per-species exponentials instead of one exponential per reaction.
@@ -27,11 +31,16 @@
 namespace pyro {
 namespace {
 
-constexpr int kCgStride = kTile * 16;           // bytes per species row of the C/G tile
-constexpr int kQBuf = kChunk * kTile * 8;       // bytes per chunk buffer
+constexpr int kRow = kTile * 16;          // bytes per species row: C[64] then G[64]
+constexpr int kQBuf = kChunk * kTile * 8; // bytes per chunk buffer
 
-__device__ inline double2 lds_cg(const unsigned char* lds, int off, int lane) {
-    return *reinterpret_cast<const double2*>(lds + off + lane * 16);
+struct CG {
+    double c, g;
+};
+
+__device__ inline CG lds_cg(const unsigned char* lds, int off, int lane) {
+    const double* p = reinterpret_cast<const double*>(lds + off) + lane;
+    return CG{p[0], p[kTile]};
 }
 
 // 1/x from the hardware estimate refined by two Newton steps
@@ -56,30 +65,23 @@ __device__ inline double log_arrhenius(const double* __restrict__ params, int ro
     return fma(-p[2], invRT, fma(p[1], lnT, p[0]));
 }
 
+// Head of the wave's queue of third-body concentrations; the queue is
+// popped by shifting, so the values stay in registers with static indices.
+template <int N>
+__device__ inline double pop_front(double (&v)[N]) {
+    const double head = v[0];
+#pragma unroll
+    for (int i = 0; i + 1 < N; ++i) v[i] = v[i + 1];
+    return head;
+}
+
 // Rate of progress of one reaction for the calling lane's cell, given its
-// Arrhenius coefficient kf.
+// Arrhenius coefficient kf and, for third-body and falloff reactions, [M].
 __device__ inline double rate_of_progress(const DevMech& m, const RxnRec& r,
                                           const double* __restrict__ params,
                                           const unsigned char* lds, int lane, double kf,
-                                          double Tc, double lnT, double invT,
+                                          double M, double Tc, double lnT, double invT,
                                           double invRT, double rtp, double irtp) {
-    double M = 1.0;
-    if (r.cls >= kThirdBody) {
-        // [M] = sum_k eps_k C_k
-        const double* e = m.eff + size_t(r.pd) * m.s_pad;
-        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-        for (int k = 0; k < m.s_pad; k += 8) {
-            a0 = fma(e[k + 0], lds_cg(lds, (k + 0) * kCgStride, lane).x, a0);
-            a1 = fma(e[k + 1], lds_cg(lds, (k + 1) * kCgStride, lane).x, a1);
-            a2 = fma(e[k + 2], lds_cg(lds, (k + 2) * kCgStride, lane).x, a2);
-            a3 = fma(e[k + 3], lds_cg(lds, (k + 3) * kCgStride, lane).x, a3);
-            a0 = fma(e[k + 4], lds_cg(lds, (k + 4) * kCgStride, lane).x, a0);
-            a1 = fma(e[k + 5], lds_cg(lds, (k + 5) * kCgStride, lane).x, a1);
-            a2 = fma(e[k + 6], lds_cg(lds, (k + 6) * kCgStride, lane).x, a2);
-            a3 = fma(e[k + 7], lds_cg(lds, (k + 7) * kCgStride, lane).x, a3);
-        }
-        M = (a0 + a1) + (a2 + a3);
-    }
     if (r.cls >= kLindemann) {
         const double k0 = exp(log_arrhenius(params, m.R + r.fo, lnT, invRT));
         const double Pr = k0 * M / kf;
@@ -99,28 +101,28 @@ __device__ inline double rate_of_progress(const DevMech& m, const RxnRec& r,
         kf = kf * (Pr / (1.0 + Pr)) * F;
     }
     // forward term k prod_r C_r
-    double2 a = lds_cg(lds, r.r[0], lane);
-    double cr = a.x, gr = a.y;
+    CG a = lds_cg(lds, r.r[0], lane);
+    double cr = a.c, gr = a.g;
     if (r.nr > 1) {
-        const double2 b = lds_cg(lds, r.r[1], lane);
-        cr *= b.x;
-        gr *= b.y;
+        const CG b = lds_cg(lds, r.r[1], lane);
+        cr *= b.c;
+        gr *= b.g;
         if (r.nr > 2) {
-            const double2 c = lds_cg(lds, r.r[2], lane);
-            cr *= c.x;
-            gr *= c.y;
+            const CG c = lds_cg(lds, r.r[2], lane);
+            cr *= c.c;
+            gr *= c.g;
         }
     }
     double q = kf * cr;
     if (r.rev) {
-        double2 p = lds_cg(lds, r.p[0], lane);
-        double cgp = p.x * p.y;
+        const CG p = lds_cg(lds, r.p[0], lane);
+        double cgp = p.c * p.g;
         if (r.np > 1) {
-            const double2 b = lds_cg(lds, r.p[1], lane);
-            cgp *= b.x * b.y;
+            const CG b = lds_cg(lds, r.p[1], lane);
+            cgp *= b.c * b.g;
             if (r.np > 2) {
-                const double2 c = lds_cg(lds, r.p[2], lane);
-                cgp *= c.x * c.y;
+                const CG c = lds_cg(lds, r.p[2], lane);
+                cgp *= c.c * c.g;
             }
         }
         double pw = 1.0;
@@ -134,7 +136,7 @@ __device__ inline double rate_of_progress(const DevMech& m, const RxnRec& r,
     return q;
 }
 
-template <int MAXOWN>
+template <int MAXOWN, int MAXPD>
 __global__ __launch_bounds__(kWaves * 64) void wdot_f64_kernel(
     DevMech m, int64_t n, int64_t ld, const double* __restrict__ rho,
     const double* __restrict__ T, const double* __restrict__ Y,
@@ -174,20 +176,31 @@ __global__ __launch_bounds__(kWaves * 64) void wdot_f64_kernel(
             const double g_lo = gibbs_poly(s.lo, Tc, omlnT, invT);
             const double g_hi = gibbs_poly(s.hi, Tc, omlnT, invT);
             const double gRT = Tc <= s.t_mid ? g_lo : g_hi;
-            *reinterpret_cast<double2*>(lds + k * kCgStride + lane * 16) =
-                make_double2(Ck, exp(gRT));
+            double* row = reinterpret_cast<double*>(lds + k * kRow) + lane;
+            row[0] = Ck;
+            row[kTile] = exp(gRT);
         }
     }
-    if (w == 0)
-        for (int k = m.S; k < m.s_pad; ++k)
-            *reinterpret_cast<double2*>(lds + k * kCgStride + lane * 16) = make_double2(0.0, 0.0);
     __syncthreads();
+
+    // ---- third-body concentrations of this wave's reactions
+    double Mr[MAXPD];
+#pragma unroll
+    for (int i = 0; i < MAXPD; ++i) Mr[i] = 0.0;
+    if (m.n_pdw[w] > 0) {
+        const double* ew = m.effw + size_t(w) * m.S * kMaxPd;
+        for (int k = 0; k < m.S; ++k) {
+            const double ck = reinterpret_cast<const double*>(lds + k * kRow)[lane];
+#pragma unroll
+            for (int i = 0; i < MAXPD; ++i) Mr[i] = fma(ew[k * kMaxPd + i], ck, Mr[i]);
+        }
+    }
 
     // ---- reaction chunks and gathering
     double acc[MAXOWN];
 #pragma unroll
     for (int i = 0; i < MAXOWN; ++i) acc[i] = 0.0;
-    unsigned char* qbase = lds + size_t(m.s_pad) * kCgStride;
+    unsigned char* qbase = lds + size_t(m.S) * kRow;
     static_assert(kRxnPerWave == 2, "the reaction phase handles reactions in pairs");
     for (int ch = 0; ch < m.n_chunks; ++ch) {
         unsigned char* qb = qbase + (ch & 1) * kQBuf;
@@ -197,12 +210,15 @@ __global__ __launch_bounds__(kWaves * 64) void wdot_f64_kernel(
         // both Arrhenius exponentials in one block, so they interleave
         const double kf0 = exp(log_arrhenius(params, r0.prow, lnT, invRT));
         const double kf1 = exp(log_arrhenius(params, r1.prow, lnT, invRT));
+        // the wave meets its third-body/falloff reactions in queue order
+        const double M0 = r0.cls >= kThirdBody ? pop_front(Mr) : 1.0;
+        const double M1 = r1.cls >= kThirdBody ? pop_front(Mr) : 1.0;
         if (r0.cls != kNoReaction)
-            *reinterpret_cast<double*>(qb + r0.qoff + lane * 8) =
-                rate_of_progress(m, r0, params, lds, lane, kf0, Tc, lnT, invT, invRT, rtp, irtp);
+            *reinterpret_cast<double*>(qb + r0.qoff + lane * 8) = rate_of_progress(
+                m, r0, params, lds, lane, kf0, M0, Tc, lnT, invT, invRT, rtp, irtp);
         if (r1.cls != kNoReaction)
-            *reinterpret_cast<double*>(qb + r1.qoff + lane * 8) =
-                rate_of_progress(m, r1, params, lds, lane, kf1, Tc, lnT, invT, invRT, rtp, irtp);
+            *reinterpret_cast<double*>(qb + r1.qoff + lane * 8) = rate_of_progress(
+                m, r1, params, lds, lane, kf1, M1, Tc, lnT, invT, invRT, rtp, irtp);
         __syncthreads();
         // gather: the boundaries of all owned species in one scalar load,
         // then each species' entries in pairs
@@ -240,38 +256,49 @@ __global__ __launch_bounds__(kWaves * 64) void wdot_f64_kernel(
     }
 }
 
-template <int MAXOWN>
+template <int MAXOWN, int MAXPD>
 hipError_t launch_f64(const pyro_mech* m, int64_t n, int64_t ld, const double* rho,
                       const double* T, const double* Y, double* wdot,
                       const double* params, hipStream_t stream) {
     const size_t lds = production_rates_lds_bytes(m);
     const int64_t blocks = (n + kTile - 1) / kTile;
-    hipLaunchKernelGGL(wdot_f64_kernel<MAXOWN>, dim3(unsigned(blocks)), dim3(kWaves * 64),
-                       lds, stream, m->dev, n, ld, rho, T, Y, wdot,
+    hipLaunchKernelGGL((wdot_f64_kernel<MAXOWN, MAXPD>), dim3(unsigned(blocks)),
+                       dim3(kWaves * 64), lds, stream, m->dev, n, ld, rho, T, Y, wdot,
                        params ? params : m->dev.params);
     return hipGetLastError();
+}
+
+// Kernel instances: (species owned per wave, [M] slots per wave).
+template <int MAXOWN, int MAXPD>
+hipError_t set_lds(int bytes) {
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&wdot_f64_kernel<MAXOWN, MAXPD>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+}
+
+template <int MAXPD>
+hipError_t dispatch_own(const pyro_mech* m, int64_t n, int64_t ld, const double* r,
+                        const double* t, const double* y, double* o, const double* params,
+                        hipStream_t stream) {
+    if (m->max_own <= 8) return launch_f64<8, MAXPD>(m, n, ld, r, t, y, o, params, stream);
+    if (m->max_own <= 16) return launch_f64<16, MAXPD>(m, n, ld, r, t, y, o, params, stream);
+    if (m->max_own <= 32) return launch_f64<32, MAXPD>(m, n, ld, r, t, y, o, params, stream);
+    return launch_f64<64, MAXPD>(m, n, ld, r, t, y, o, params, stream);
 }
 
 }  // namespace
 
 size_t production_rates_lds_bytes(const pyro_mech* m) {
-    const int s_pad = (m->S + 7) / 8 * 8;
-    return size_t(s_pad) * kCgStride + 2 * size_t(kQBuf);
+    return size_t(m->S) * kRow + 2 * size_t(kQBuf);
 }
 
 hipError_t prepare_production_rates(const pyro_mech* m) {
     const int lds = int(production_rates_lds_bytes(m));
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&wdot_f64_kernel<8>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    if (e == hipSuccess)
-        e = hipFuncSetAttribute(reinterpret_cast<const void*>(&wdot_f64_kernel<16>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    if (e == hipSuccess)
-        e = hipFuncSetAttribute(reinterpret_cast<const void*>(&wdot_f64_kernel<32>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    if (e == hipSuccess)
-        e = hipFuncSetAttribute(reinterpret_cast<const void*>(&wdot_f64_kernel<64>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    hipError_t e = hipSuccess;
+    const hipError_t all[] = {set_lds<8, 8>(lds),  set_lds<16, 8>(lds),  set_lds<32, 8>(lds),
+                              set_lds<64, 8>(lds), set_lds<8, 16>(lds),  set_lds<16, 16>(lds),
+                              set_lds<32, 16>(lds), set_lds<64, 16>(lds)};
+    for (hipError_t x : all)
+        if (x != hipSuccess) e = x;
     return e;
 }
 
@@ -283,10 +310,8 @@ hipError_t launch_production_rates(const pyro_mech* m, int64_t n, int64_t ld, in
     const double* t = static_cast<const double*>(T);
     const double* y = static_cast<const double*>(Y);
     double* o = static_cast<double*>(wdot);
-    if (m->max_own <= 8) return launch_f64<8>(m, n, ld, r, t, y, o, params, stream);
-    if (m->max_own <= 16) return launch_f64<16>(m, n, ld, r, t, y, o, params, stream);
-    if (m->max_own <= 32) return launch_f64<32>(m, n, ld, r, t, y, o, params, stream);
-    return launch_f64<64>(m, n, ld, r, t, y, o, params, stream);
+    if (m->max_pdw <= 8) return dispatch_own<8>(m, n, ld, r, t, y, o, params, stream);
+    return dispatch_own<16>(m, n, ld, r, t, y, o, params, stream);
 }
 
 }  // namespace pyro

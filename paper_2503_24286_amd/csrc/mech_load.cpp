@@ -272,17 +272,27 @@ int load_mechanism(const char* path, pyro_mech** out) {
         std::memset(&r, 0, sizeof(r));
         r.cls = kNoReaction;
     }
-    std::vector<int> slot_of(R, -1), chunk_of(R, -1);
+    std::vector<int> slot_of(R, -1), chunk_of(R, -1), wave_of(R, -1);
+    std::vector<std::vector<int>> pd_of_wave(kWaves);
     const int cg_stride = kTile * 16;  // bytes per species row of the C/G tile
     for (int c = 0; c < n_chunks; ++c) {
         std::vector<double> wl(kWaves, 0.0);
         std::vector<int> used(kWaves, 0);
         for (int t = c * kChunk; t < std::min(R, (c + 1) * kChunk); ++t) {
             const int j = rorder[t];
+            const bool is_pd = f.rtype[j] >= 1;
             int best = -1;
             for (int w = 0; w < kWaves; ++w)
-                if (used[w] < kRxnPerWave && (best < 0 || wl[w] < wl[best])) best = w;
+                if (used[w] < kRxnPerWave && !(is_pd && int(pd_of_wave[w].size()) == kMaxPd) &&
+                    (best < 0 || wl[w] < wl[best]))
+                    best = w;
+            if (best < 0) {
+                delete m;
+                return fail(PYRO_E_UNSUPPORTED, "too many third-body and falloff reactions");
+            }
             const int slot = best * kRxnPerWave + used[best]++;
+            wave_of[j] = best;
+            if (is_pd) pd_of_wave[best].push_back(j);
             wl[best] += cost(j);
             slot_of[j] = slot;
             chunk_of[j] = c;
@@ -297,7 +307,7 @@ int load_mechanism(const char* path, pyro_mech** out) {
             }
             r.dnu = dnu[j];
             r.prow = j;
-            r.pd = pd_row[j];
+            r.pdw = is_pd ? int(pd_of_wave[best].size()) - 1 : -1;
             r.fo = fo_idx[j];
             r.qoff = slot * kTile * 8;
         }
@@ -366,9 +376,20 @@ int load_mechanism(const char* path, pyro_mech** out) {
         fr[i].a2 = -t[3];
     }
     const int s_pad = (S + 7) / 8 * 8;
-    std::vector<double> eff(size_t(std::max(n_pd, 1)) * s_pad, 0.0);
-    for (int i = 0; i < n_pd; ++i)
-        for (int k = 0; k < S; ++k) eff[size_t(i) * s_pad + k] = f.eff[size_t(i) * S + k];
+    // efficiencies by (wave, species, wave slot): the [M] pass of a wave
+    // reads the kMaxPd values of one species with one scalar load
+    std::vector<double> effw(size_t(kWaves) * S * kMaxPd, 0.0);
+    std::vector<int32_t> n_pdw(kWaves, 0);
+    m->max_pdw = 0;
+    for (int w = 0; w < kWaves; ++w) {
+        n_pdw[w] = int(pd_of_wave[w].size());
+        m->max_pdw = std::max(m->max_pdw, n_pdw[w]);
+        for (int i = 0; i < n_pdw[w]; ++i) {
+            const int row = pd_row[pd_of_wave[w][i]];
+            for (int k = 0; k < S; ++k)
+                effw[(size_t(w) * S + k) * kMaxPd + i] = f.eff[size_t(row) * S + k];
+        }
+    }
     std::vector<int32_t> own_tab(kWaves * kMaxOwn, -1), n_own(kWaves);
     for (int w = 0; w < kWaves; ++w) {
         n_own[w] = int(own[w].size());
@@ -383,7 +404,8 @@ int load_mechanism(const char* path, pyro_mech** out) {
         {sp.data(), sp.size() * sizeof(SpeciesRec), 0},
         {recs.data(), recs.size() * sizeof(RxnRec), 0},
         {fr.data(), fr.size() * sizeof(FalloffRec), 0},
-        {eff.data(), eff.size() * sizeof(double), 0},
+        {effw.data(), effw.size() * sizeof(double), 0},
+        {n_pdw.data(), n_pdw.size() * sizeof(int32_t), 0},
         {params.data(), params.size() * sizeof(double), 0},
         {own_tab.data(), own_tab.size() * sizeof(int32_t), 0},
         {n_own.data(), n_own.size() * sizeof(int32_t), 0},
@@ -429,14 +451,15 @@ int load_mechanism(const char* path, pyro_mech** out) {
     d.species = reinterpret_cast<const SpeciesRec*>(base + parts[0].off);
     d.rxn = reinterpret_cast<const RxnRec*>(base + parts[1].off);
     d.falloff = reinterpret_cast<const FalloffRec*>(base + parts[2].off);
-    d.eff = reinterpret_cast<const double*>(base + parts[3].off);
-    d.params = reinterpret_cast<const double*>(base + parts[4].off);
-    d.own = reinterpret_cast<const int32_t*>(base + parts[5].off);
-    d.n_own = reinterpret_cast<const int32_t*>(base + parts[6].off);
-    d.gptr = reinterpret_cast<const int32_t*>(base + parts[7].off);
-    d.gent = reinterpret_cast<const GatherEntry*>(base + parts[8].off);
-    d.newton = reinterpret_cast<const NewtonSpecies*>(base + parts[9].off);
-    d.w = reinterpret_cast<const double*>(base + parts[10].off);
+    d.effw = reinterpret_cast<const double*>(base + parts[3].off);
+    d.n_pdw = reinterpret_cast<const int32_t*>(base + parts[4].off);
+    d.params = reinterpret_cast<const double*>(base + parts[5].off);
+    d.own = reinterpret_cast<const int32_t*>(base + parts[6].off);
+    d.n_own = reinterpret_cast<const int32_t*>(base + parts[7].off);
+    d.gptr = reinterpret_cast<const int32_t*>(base + parts[8].off);
+    d.gent = reinterpret_cast<const GatherEntry*>(base + parts[9].off);
+    d.newton = reinterpret_cast<const NewtonSpecies*>(base + parts[10].off);
+    d.w = reinterpret_cast<const double*>(base + parts[11].off);
     err = prepare_production_rates(m);
     if (err != hipSuccess) {
         (void)hipFree(m->blob);

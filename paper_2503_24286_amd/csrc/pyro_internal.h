@@ -27,6 +27,9 @@ constexpr int kRxnPerWave = 2;
 constexpr int kChunk = kWaves * kRxnPerWave;
 // Max species a wave owns (accumulates) in the production-rate kernel.
 constexpr int kMaxOwn = 64;
+// Max third-body/falloff reactions a wave evaluates per tile; their [M]
+// live in registers of that wave.
+constexpr int kMaxPd = 16;
 // Max molecules per reaction side.
 constexpr int kMaxSide = 3;
 // Max distinct T_mid values among the species (Newton kernel groups).
@@ -46,7 +49,7 @@ struct RxnRec {
     int32_t p[kMaxSide];  // byte offsets of the product slots
     int32_t dnu;          // sum of the net stoichiometric coefficients
     int32_t prow;         // row of the Arrhenius triple (the reaction index)
-    int32_t pd;           // row of the efficiency table, -1 if none
+    int32_t pdw;          // position in the evaluating wave's [M] queue, -1 if none
     int32_t fo;           // falloff index, -1 if none
     int32_t qoff;         // byte offset of the rate-of-progress slot in a chunk
     int32_t pad;
@@ -100,7 +103,8 @@ struct DevMech {
     const SpeciesRec* species;           // [S]
     const RxnRec* rxn;                   // [n_chunks][kWaves][kRxnPerWave]
     const FalloffRec* falloff;           // [n_fo]
-    const double* eff;                   // [n_pd][s_pad]
+    const double* effw;                  // [kWaves][S][kMaxPd] efficiencies by wave slot
+    const int32_t* n_pdw;                // [kWaves] third-body/falloff reactions per wave
     const double* params;                // [R + n_fo][3] default triples
     const int32_t* own;                  // [kWaves][kMaxOwn] species owned
     const int32_t* n_own;                // [kWaves]
@@ -117,6 +121,7 @@ struct pyro_mech {
     int S = 0, R = 0, E = 0, n_tb = 0, n_fo = 0;
     int nnz_f = 0, nnz_r = 0, nnz_net = 0;
     int max_own = 0;
+    int max_pdw = 0;
     std::vector<double> W;               // host copy
     std::vector<double> params;          // host copy of the default triples
     pyro::DevMech dev{};
