@@ -125,6 +125,32 @@ PYRO_API int pyro_production_rates(const pyro_mech* mech, int64_t n, int64_t ld,
                           void* stream);
 
 /*
+ * Reverse-mode product of the net production rates.  With
+ * L = sum_cells sum_k wbar_k(cell) omega_k(cell) at fixed density, returns
+ * the per-cell gradients dL/dY and dL/dT and the gradients with respect to
+ * every Arrhenius triple summed over the cells (reverse sweep of the
+ * equations named for pyro_production_rates; third-body efficiencies and
+ * Troe shape parameters get no gradient).
+ *
+ *   rho[n], T[n], Y[S*ld]  the state (as for pyro_production_rates)
+ *   wbar[S*ld]             dL/d omega
+ *   Ybar[S*ld]             output dL/dY (zero where Y_k <= 0)
+ *   Tbar[n]                output dL/dT
+ *   params_bar             device array of 3*n_params doubles, overwritten
+ *                          with dL/d(ln A, b, Ea) in the row order of params
+ *                          (Ea per J/mol); deterministic (fixed-order sums)
+ *   params                 Arrhenius triples to differentiate at, or NULL
+ * The call allocates a temporary workspace on the stream (stream-ordered).
+ * FP64 only.  PYRO_E_UNSUPPORTED for mechanisms whose tables exceed the
+ * kernel's LDS tile or more than 512 reactions.
+ */
+PYRO_API int pyro_production_rates_vjp(const pyro_mech* mech, int64_t n, int64_t ld,
+                                       const double* rho, const double* T,
+                                       const double* Y, const double* wbar,
+                                       double* Ybar, double* Tbar, double* params_bar,
+                                       const double* params, void* stream);
+
+/*
  * Temperature from the mass-specific internal energy by Newton iteration
  * (Appendix A.3.1: eq. int_energy, eq. delta_temp, eq. cv):
  * T <- T - (Y.e(T) - e)/c_v(T), per cell, until the first update with

@@ -6,5 +6,6 @@ include/pyro.h.
 """
 
 from ._lib import PyroError  # noqa: F401
-from .api import (Mechanism, density, internal_energy, pressure,  # noqa: F401
-                  production_rates, temperature)
+from .api import (Mechanism, ProductionRates, density, internal_energy,  # noqa: F401
+                  pressure, production_rates, production_rates_autograd,
+                  production_rates_vjp, temperature)

@@ -166,3 +166,63 @@ def internal_energy(mech, T, Y, out=None):
     check(lib().pyro_internal_energy(mech.handle, n, ld, _ptr(T), _ptr(Y), _ptr(out),
                                      _stream(Y.device)))
     return out
+
+
+def production_rates_vjp(mech, rho, T, Y, wbar, params=None, Ybar=None, Tbar=None,
+                         params_bar=None):
+    """Gradients of L = sum wbar * omega (fixed rho): returns (Ybar, Tbar,
+    params_bar) with params_bar of shape (n_params, 3) = dL/d(ln A, b, Ea)."""
+    S = mech.n_species
+    n = Y.shape[1]
+    ld = _species_major(Y, S, torch.float64, "Y")
+    if _species_major(wbar, S, torch.float64, "wbar") != ld:
+        raise ValueError("wbar must have the row stride of Y")
+    _cells(rho, n, torch.float64, "rho")
+    _cells(T, n, torch.float64, "T")
+    if Ybar is None:
+        Ybar = torch.empty((S, ld), dtype=torch.float64, device=Y.device)[:, :n]
+    if _species_major(Ybar, S, torch.float64, "Ybar") != ld:
+        raise ValueError("Ybar must have the row stride of Y")
+    if Tbar is None:
+        Tbar = torch.empty(n, dtype=torch.float64, device=Y.device)
+    if params_bar is None:
+        params_bar = torch.empty((mech.n_params, 3), dtype=torch.float64, device=Y.device)
+    if params is not None:
+        if params.dtype != torch.float64 or params.numel() != 3 * mech.n_params:
+            raise ValueError("params must hold 3*n_params float64 values")
+        params = params.contiguous()
+    check(lib().pyro_production_rates_vjp(
+        mech.handle, n, ld, _ptr(rho), _ptr(T), _ptr(Y), _ptr(wbar), _ptr(Ybar), _ptr(Tbar),
+        _ptr(params_bar), _ptr(params), _stream(Y.device)))
+    return Ybar, Tbar, params_bar
+
+
+class ProductionRates(torch.autograd.Function):
+    """omega(rho, T, Y; params) with a reverse mode from the library's VJP
+    kernel.  The density gets no gradient (omega is differentiated at fixed
+    rho).  ``params`` is the (n_params, 3) tensor of (ln A, b, Ea)."""
+
+    @staticmethod
+    def forward(ctx, mech, rho, T, Y, params):
+        ctx.mech = mech
+        ctx.save_for_backward(rho, T, Y, params)
+        return production_rates(mech, rho, T, Y,
+                                params=None if params is None else params.detach().reshape(-1))
+
+    @staticmethod
+    def backward(ctx, grad_w):
+        rho, T, Y, params = ctx.saved_tensors
+        S, n = Y.shape
+        wbar = torch.empty((S, Y.stride(0) if S > 1 else n), dtype=torch.float64,
+                           device=Y.device)[:, :n]
+        wbar.copy_(grad_w)
+        Ybar, Tbar, pbar = production_rates_vjp(
+            ctx.mech, rho, T, Y, wbar,
+            params=None if params is None else params.detach().reshape(-1))
+        return (None, None, Tbar if ctx.needs_input_grad[2] else None,
+                Ybar if ctx.needs_input_grad[3] else None,
+                pbar if params is not None and ctx.needs_input_grad[4] else None)
+
+
+def production_rates_autograd(mech, rho, T, Y, params=None):
+    return ProductionRates.apply(mech, rho, T, Y, params)

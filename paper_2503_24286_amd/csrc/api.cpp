@@ -122,6 +122,31 @@ int pyro_production_rates(const pyro_mech* m, int64_t n, int64_t ld, int dtype, 
                     "production-rate kernel launch");
 }
 
+int pyro_production_rates_vjp(const pyro_mech* m, int64_t n, int64_t ld, const double* rho,
+                              const double* T, const double* Y, const double* wbar, double* Ybar,
+                              double* Tbar, double* params_bar, const double* params,
+                              void* stream) {
+    clear_error();
+    if (int rc = check_sizes(n, ld)) return rc;
+    if (int rc = check_mech(m)) return rc;
+    if (!params_bar) return fail(PYRO_E_ARG, "null pointer: params_bar");
+    if (vjp_lds_bytes(m) > 160 * 1024)
+        return fail(PYRO_E_UNSUPPORTED, "mechanism too large for the VJP tile");
+    if (m->dev.n_chunks > kWaves * 4)
+        return fail(PYRO_E_UNSUPPORTED, "too many reactions for the VJP kernel (at most 512)");
+    if (m->max_own > 16) return fail(PYRO_E_UNSUPPORTED, "too many species for the VJP kernel");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (n == 0) {
+        // no cells: every parameter gradient is zero
+        return launched(hipMemsetAsync(params_bar, 0, size_t(m->R + m->n_fo) * 3 * sizeof(double), s),
+                        "hipMemsetAsync");
+    }
+    if (int rc = check_ptrs({rho, T, Y, wbar, Ybar, Tbar}, "rho, T, Y, wbar, Ybar and Tbar")) return rc;
+    return launched(launch_production_rates_vjp(m, n, ld, rho, T, Y, wbar, Ybar, Tbar, params_bar,
+                                                params, s),
+                    "VJP kernel launch");
+}
+
 int pyro_temperature(const pyro_mech* m, int64_t n, int64_t ld, const double* e, const double* Y,
                      const double* T_guess, double T_guess_value, double* T_out, int32_t* status,
                      int max_iter, double rtol, void* stream) {

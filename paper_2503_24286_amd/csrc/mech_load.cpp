@@ -17,6 +17,7 @@
 //   f64 efficiency[n_third_body + n_falloff][S],
 // and a trailing u64 FNV-1a hash of every preceding byte.
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstring>
 #include <fstream>
@@ -310,6 +311,7 @@ int load_mechanism(const char* path, pyro_mech** out) {
             r.pdw = is_pd ? int(pd_of_wave[best].size()) - 1 : -1;
             r.fo = fo_idx[j];
             r.qoff = slot * kTile * 8;
+            r.pd = pd_row[j];
         }
     }
     // ---- gathering lists: (chunk, wave, owned species) -> (slot, nu)
@@ -331,6 +333,37 @@ int load_mechanism(const char* path, pyro_mech** out) {
                     }
             }
     gent.resize(gent.size() + 2, 0u);  // slack: the pairwise loop may read one past
+
+    // ---- reverse-sweep gathering lists: per participant (slot, nu', nu'')
+    std::vector<int32_t> vgptr;
+    std::vector<uint32_t> vgent;
+    {
+        std::vector<std::vector<std::array<int, 3>>> part(S);  // species -> (j, nu', nu'')
+        for (int j = 0; j < R; ++j) {
+            std::vector<int> cf(S, 0), cr(S, 0);
+            for (int k : reac[j]) cf[k]++;
+            for (int k : prod[j]) cr[k]++;
+            for (int k = 0; k < S; ++k)
+                if (cf[k] || cr[k]) part[k].push_back({j, cf[k], cr[k]});
+        }
+        for (int c = 0; c < std::max(n_chunks, 1); ++c)
+            for (int w = 0; w < kWaves; ++w)
+                for (int i = 0; i <= kMaxOwn; ++i) {
+                    vgptr.push_back(int32_t(vgent.size()));
+                    if (i == kMaxOwn || i >= int(own[w].size())) continue;
+                    for (auto& e : part[own[w][i]])
+                        if (chunk_of[e[0]] == c)
+                            vgent.push_back(uint32_t(slot_of[e[0]] * kTile * 8) |
+                                            (uint32_t(e[1]) << 16) | (uint32_t(e[2]) << 24));
+                }
+        vgent.resize(vgent.size() + 2, 0u);
+    }
+    std::vector<int32_t> chunk_fo(std::max(n_chunks, 1), 0);
+    for (int j = 0; j < R; ++j)
+        if (f.rtype[j] >= 2) chunk_fo[chunk_of[j]] = 1;
+    std::vector<double> eff_t(size_t(S) * std::max(n_pd, 1), 0.0);
+    for (int i = 0; i < n_pd; ++i)
+        for (int k = 0; k < S; ++k) eff_t[size_t(k) * std::max(n_pd, 1) + i] = f.eff[size_t(i) * S + k];
 
     // ---- species tables
     std::vector<SpeciesRec> sp(S);
@@ -413,6 +446,10 @@ int load_mechanism(const char* path, pyro_mech** out) {
         {gent.data(), gent.size() * sizeof(GatherEntry), 0},
         {ns.data(), ns.size() * sizeof(NewtonSpecies), 0},
         {f.W.data(), f.W.size() * sizeof(double), 0},
+        {vgptr.data(), vgptr.size() * sizeof(int32_t), 0},
+        {vgent.data(), vgent.size() * sizeof(uint32_t), 0},
+        {eff_t.data(), eff_t.size() * sizeof(double), 0},
+        {chunk_fo.data(), chunk_fo.size() * sizeof(int32_t), 0},
     };
     size_t total = 0;
     for (auto& p : parts) {
@@ -426,6 +463,11 @@ int load_mechanism(const char* path, pyro_mech** out) {
     if (err != hipSuccess) {
         delete m;
         return hip_fail(err, "hipGetDevice");
+    }
+    err = hipDeviceGetAttribute(&m->n_cu, hipDeviceAttributeMultiprocessorCount, m->device);
+    if (err != hipSuccess) {
+        delete m;
+        return hip_fail(err, "hipDeviceGetAttribute");
     }
     err = hipMalloc(&m->blob, total);
     if (err != hipSuccess) {
@@ -460,7 +502,12 @@ int load_mechanism(const char* path, pyro_mech** out) {
     d.gent = reinterpret_cast<const GatherEntry*>(base + parts[9].off);
     d.newton = reinterpret_cast<const NewtonSpecies*>(base + parts[10].off);
     d.w = reinterpret_cast<const double*>(base + parts[11].off);
+    d.vgptr = reinterpret_cast<const int32_t*>(base + parts[12].off);
+    d.vgent = reinterpret_cast<const uint32_t*>(base + parts[13].off);
+    d.eff_t = reinterpret_cast<const double*>(base + parts[14].off);
+    d.chunk_fo = reinterpret_cast<const int32_t*>(base + parts[15].off);
     err = prepare_production_rates(m);
+    if (err == hipSuccess) err = prepare_vjp(m);
     if (err != hipSuccess) {
         (void)hipFree(m->blob);
         delete m;

@@ -52,7 +52,7 @@ struct RxnRec {
     int32_t pdw;          // position in the evaluating wave's [M] queue, -1 if none
     int32_t fo;           // falloff index, -1 if none
     int32_t qoff;         // byte offset of the rate-of-progress slot in a chunk
-    int32_t pad;
+    int32_t pd;           // row of the efficiency table, -1 if none
 };
 static_assert(sizeof(RxnRec) == 64, "RxnRec must be 64 bytes");
 
@@ -112,6 +112,11 @@ struct DevMech {
     const GatherEntry* gent;             // gathering entries
     const NewtonSpecies* newton;         // [S]
     const double* w;                     // [S] molar masses
+    // reverse sweep (VJP)
+    const int32_t* vgptr;                // [n_chunks][kWaves][kMaxOwn + 1]
+    const uint32_t* vgent;               // slot offset | nu' << 16 | nu'' << 24
+    const double* eff_t;                 // [S][n_pd] efficiencies by species
+    const int32_t* chunk_fo;             // [n_chunks] 1 if the chunk holds a falloff reaction
 };
 
 }  // namespace pyro
@@ -122,6 +127,7 @@ struct pyro_mech {
     int nnz_f = 0, nnz_r = 0, nnz_net = 0;
     int max_own = 0;
     int max_pdw = 0;
+    int n_cu = 0;                        // compute units of the device
     std::vector<double> W;               // host copy
     std::vector<double> params;          // host copy of the default triples
     pyro::DevMech dev{};
@@ -159,5 +165,12 @@ hipError_t launch_internal_energy(const pyro_mech* m, int64_t n, int64_t ld,
 // LDS bytes the production-rate kernel needs for this mechanism.
 size_t production_rates_lds_bytes(const pyro_mech* m);
 hipError_t prepare_production_rates(const pyro_mech* m);
+hipError_t launch_production_rates_vjp(const pyro_mech* m, int64_t n, int64_t ld,
+                                       const double* rho, const double* T, const double* Y,
+                                       const double* wbar, double* Ybar, double* Tbar,
+                                       double* params_bar, const double* params,
+                                       hipStream_t stream);
+size_t vjp_lds_bytes(const pyro_mech* m);
+hipError_t prepare_vjp(const pyro_mech* m);
 
 }  // namespace pyro

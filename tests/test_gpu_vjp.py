@@ -1,0 +1,264 @@
+"""The HIP reverse-mode kernel (pyro_production_rates_vjp) against the
+oracle's complex-step gradients, central differences of the HIP forward
+kernel, conservation invariants and the autograd wrapper."""
+
+import numpy as np
+import pytest
+
+import mechs
+from gpu_util import announce, states, to_dev, torch_cuda
+from oracle import gradients, kinetics, thermo
+from oracle.constants import GAS_CONSTANT as RU
+from pyro_synth.states import draw_cotangent
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def lib_mechs():
+    torch = torch_cuda()
+    import paper_2503_24286_amd as pyro
+    out = {c: pyro.Mechanism(mechs.config_path(c)) for c in (0, 1)}
+    yield torch, pyro, out
+    for m in out.values():
+        m.close()
+
+
+def _gpu_vjp(torch, pyro, gm, rho, T, Y, wbar, params=None):
+    r, t, y, wb = to_dev(torch, rho, T, Y, wbar)
+    p = None if params is None else to_dev(torch, params.reshape(-1))[0]
+    Yb, Tb, pb = pyro.production_rates_vjp(gm, r, t, y, wb, params=p)
+    torch.cuda.synchronize()
+    return Yb.cpu().numpy(), Tb.cpu().numpy(), pb.cpu().numpy()
+
+
+def _scales(m, rho, T, Y, wbar, abs_qbar=False):
+    """Magnitudes of the terms summed into each gradient (no cancellation):
+    the reference the errors are measured against.  With ``abs_qbar`` the
+    cotangent of each rate of progress is taken as |nu|^T |wbar|, the size of
+    the terms that cancel in nu^T wbar."""
+    Rf, Rr, phi, q = kinetics.rates_of_progress(m, rho, T, Y)
+    qbar = np.abs(m.nu).T @ np.abs(wbar) if abs_qbar else m.nu.T @ wbar
+    Dbar = np.abs(qbar * phi)
+    a = Dbar * np.abs(Rf)
+    b = Dbar * np.abs(Rr)
+    ab = a + b
+    pos = Y > 0
+    sY = (m.nu_f @ a + m.nu_r @ b) / np.where(pos, Y, 1.0)
+    M = np.zeros_like(Rf)
+    pd = m.pd_reactions
+    if len(pd):
+        M[pd] = np.abs(qbar[pd]) * (np.abs(Rf[pd]) + np.abs(Rr[pd]))
+        eps = np.zeros((m.S, m.R))
+        eps[:, pd] = m.efficiency.T
+        sY = sY + (rho / m.W[:, None]) * (eps @ M)
+    sY = np.where(pos, sY, 0.0)     # dL/dY_k = 0 exactly where Y_k <= 0
+    h = np.abs(thermo.species_h_RT(m, T)).max(axis=0)
+    coef = (np.abs(m.arrhenius[:, 1])[:, None] + m.arrhenius[:, 2][:, None] / (RU * T)
+            + np.abs(m.nu.sum(axis=0))[:, None] + 2.0 + 2.0 * h[None, :])
+    sT = (ab * coef).sum(axis=0) / T
+    sP = np.zeros((m.R + m.n_falloff, 3))
+    sP[:m.R, 0] = ab.sum(axis=1)
+    sP[:m.R, 1] = (ab * np.abs(np.log(T))).sum(axis=1)
+    sP[:m.R, 2] = (ab / (RU * T)).sum(axis=1)
+    for f, j in enumerate(m.falloff_reactions):
+        sP[m.R + f] = sP[j]
+    return sY, sT, sP
+
+
+def _check_vs_oracle(m, rho, T, Y, wbar, Yb, Tb, pb, tol=TOL):
+    Yr, Tr, pr = gradients.vjp(m, rho, T, Y, wbar)
+    sY, sT, sP = _scales(m, rho, T, Y, wbar)
+    assert np.array_equal(Yb[sY == 0], Yr[sY == 0])
+    eY = np.where(sY > 0, np.abs(Yb - Yr) / np.where(sY > 0, sY, 1.0), 0.0)
+    eT = np.abs(Tb - Tr) / np.maximum(sT, 1e-300)
+    eP = np.abs(pb - pr) / np.maximum(sP, 1e-300)
+    announce(f"  vjp errors: Y {eY.max():.2e}  T {eT.max():.2e}  params {eP.max():.2e}")
+    assert eY.max() <= tol, f"Ybar error {eY.max():.3e} at {np.unravel_index(eY.argmax(), eY.shape)}"
+    assert eT.max() <= tol, f"Tbar error {eT.max():.3e}"
+    assert eP.max() <= tol, f"params_bar error {eP.max():.3e} at {np.unravel_index(eP.argmax(), eP.shape)}"
+    assert np.all(Yb[Y <= 0] == 0.0)
+
+
+@pytest.mark.parametrize("cfg,n", [(0, 130), (1, 70)])
+def test_vjp_matches_complex_step_oracle(lib_mechs, cfg, n):
+    torch, pyro, gms = lib_mechs
+    m = mechs.load_config(cfg)
+    T, p, Y, rho = states(cfg, n, m.S, first=11)
+    wbar = draw_cotangent(2, n, m.S)
+    announce(f"vjp cfg{cfg} n={n}")
+    Yb, Tb, pb = _gpu_vjp(torch, pyro, gms[cfg], rho, T, Y, wbar)
+    _check_vs_oracle(m, rho, T, Y, wbar, Yb, Tb, pb)
+
+
+def test_vjp_degenerate_states(lib_mechs):
+    torch, pyro, gms = lib_mechs
+    m = mechs.load_config(1)
+    n = 70
+    T, p, Y, rho = states(1, n, m.S, first=700)
+    Y[4, :10] = 0.0
+    Y[9, 10:20] = -1e-4
+    T[20:25] = m.T_mid[0]
+    wbar = draw_cotangent(2, n, m.S, seed=5)
+    announce("vjp degenerate states")
+    Yb, Tb, pb = _gpu_vjp(torch, pyro, gms[1], rho, T, Y, wbar)
+    _check_vs_oracle(m, rho, T, Y, wbar, Yb, Tb, pb)
+
+
+def test_vjp_conserved_combinations_have_zero_gradient(lib_mechs):
+    """sum_k W_k omega_k = 0 for every state, so its gradient vanishes."""
+    torch, pyro, gms = lib_mechs
+    m = mechs.load_config(1)
+    n = 200
+    T, p, Y, rho = states(1, n, m.S, first=300)
+    announce("vjp invariants")
+    for wbar in (np.repeat(m.W[:, None], n, axis=1),
+                 np.repeat(m.composition[2][:, None].astype(float), n, axis=1)):
+        Yb, Tb, pb = _gpu_vjp(torch, pyro, gms[1], rho, T, Y, wbar)
+        sY, sT, sP = _scales(m, rho, T, Y, wbar, abs_qbar=True)
+        assert np.all(Yb[sY == 0] == 0.0)
+        assert np.max(np.abs(Yb) / np.where(sY > 0, sY, 1.0)) <= TOL
+        assert np.max(np.abs(Tb) / sT) <= TOL
+        assert np.max(np.abs(pb) / np.maximum(sP, 1e-300)) <= TOL
+
+
+def test_vjp_matches_central_differences_of_the_forward_kernel(lib_mechs):
+    """64 random cells of the 53-species workload; h = 1e-6 relative (floors
+    ln A 1, b 1, Ea 1e4 J/mol, Y 1e-20); |fd - g| <= 1e-5 |g| + rounding floor
+    30 eps |L|_abs / h."""
+    torch, pyro, gms = lib_mechs
+    gm = gms[1]
+    m = mechs.load_config(1)
+    n = 64
+    rng = np.random.default_rng(64)
+    first = int(rng.integers(0, (1 << 20) - n))
+    T, p, Y, rho = states(2, n, m.S, first=first)
+    wbar = draw_cotangent(2, n, m.S, seed=77)
+    announce("vjp vs central differences")
+    Yb, Tb, pb = _gpu_vjp(torch, pyro, gm, rho, T, Y, wbar)
+    r_d, w_d = to_dev(torch, rho, wbar)
+    P = m.parameters()
+
+    def cellL(Tc, Yc, Pc=None):
+        t, y = to_dev(torch, Tc, Yc)
+        pp = None if Pc is None else to_dev(torch, Pc.reshape(-1))[0]
+        w = pyro.production_rates(gm, r_d, t, y, params=pp)
+        return (w_d * w).sum(dim=0).cpu().numpy(), (w_d * w).abs().sum(dim=0).cpu().numpy()
+
+    eps = np.finfo(float).eps
+    checked = resolved = 0
+    L0, Labs = cellL(T, Y)
+    for k in range(m.S):
+        h = 1e-6 * np.maximum(Y[k], 1e-20)
+        Yp, Ym = Y.copy(), Y.copy()
+        Yp[k] += h
+        Ym[k] -= h
+        fd = (cellL(T, Yp)[0] - cellL(T, Ym)[0]) / (2 * h)
+        floor = 30 * eps * Labs / h
+        ok = (Y[k] > 2 * h)                      # stay on one side of max(Y, 0)
+        assert np.all((np.abs(fd - Yb[k]) <= 1e-5 * np.abs(Yb[k]) + floor)[ok])
+        checked += ok.sum()
+        resolved += (ok & (np.abs(Yb[k]) > 1e3 * floor)).sum()
+    h = 1e-6 * T
+    fd = (cellL(T + h, Y)[0] - cellL(T - h, Y)[0]) / (2 * h)
+    floor = 30 * eps * Labs / h
+    assert np.all(np.abs(fd - Tb) <= 1e-5 * np.abs(Tb) + floor)
+    checked += n
+    resolved += (np.abs(Tb) > 1e3 * floor).sum()
+    floors = (1.0, 1.0, 1e4)
+    rows = list(range(0, m.R, 7)) + list(range(m.R, m.R + m.n_falloff))
+    for j in rows:
+        for c in range(3):
+            hh = 1e-6 * max(abs(P[j, c]), floors[c])
+            Pp, Pm = P.copy(), P.copy()
+            Pp[j, c] += hh
+            Pm[j, c] -= hh
+            fd = (cellL(T, Y, Pp)[0].sum() - cellL(T, Y, Pm)[0].sum()) / (2 * hh)
+            floor = 30 * eps * Labs.sum() / hh
+            assert abs(fd - pb[j, c]) <= 1e-5 * abs(pb[j, c]) + floor, (j, c, fd, pb[j, c])
+            checked += 1
+            resolved += abs(pb[j, c]) > 1e3 * floor
+    # the synthetic rates span ~60 decades, so most single entries sit below
+    # the differences' rounding floor; hundreds are still resolved sharply
+    announce(f"  resolved {resolved}/{checked}")
+    assert resolved >= 300 and resolved >= 0.1 * checked
+
+
+def test_vjp_is_deterministic_and_linear(lib_mechs):
+    torch, pyro, gms = lib_mechs
+    m = mechs.load_config(1)
+    n = 5000
+    T, p, Y, rho = states(1, n, m.S, first=900)
+    w1 = draw_cotangent(2, n, m.S, seed=1)
+    w2 = draw_cotangent(2, n, m.S, seed=2)
+    announce("vjp determinism and linearity")
+    a = _gpu_vjp(torch, pyro, gms[1], rho, T, Y, w1)
+    b = _gpu_vjp(torch, pyro, gms[1], rho, T, Y, w1)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+    c = _gpu_vjp(torch, pyro, gms[1], rho, T, Y, w2)
+    d = _gpu_vjp(torch, pyro, gms[1], rho, T, Y, w1 + w2)
+    sP = _scales(m, rho, T, Y, np.abs(w1) + np.abs(w2))[2]
+    assert np.max(np.abs(d[2] - a[2] - c[2]) / np.maximum(sP, 1e-300)) <= 1e-12
+
+
+def test_autograd_function(lib_mechs):
+    torch, pyro, gms = lib_mechs
+    m = mechs.load_config(0)
+    n = 300
+    T, p, Y, rho = states(0, n, m.S)
+    wbar = draw_cotangent(0, n, m.S)
+    announce("autograd")
+    r, t, y, wb = to_dev(torch, rho, T, Y, wbar)
+    params = torch.from_numpy(m.parameters()).cuda().requires_grad_(True)
+    t.requires_grad_(True)
+    y.requires_grad_(True)
+    w = pyro.production_rates_autograd(gms[0], r, t, y, params)
+    (w * wb).sum().backward()
+    Yb, Tb, pb = _gpu_vjp(torch, pyro, gms[0], rho, T, Y, wbar)
+    assert np.array_equal(y.grad.cpu().numpy(), Yb)
+    assert np.array_equal(t.grad.cpu().numpy(), Tb)
+    assert np.array_equal(params.grad.cpu().numpy(), pb)
+
+
+def test_vjp_zero_cells_zeroes_parameter_gradients(lib_mechs):
+    torch, pyro, gms = lib_mechs
+    gm = gms[1]
+    e = torch.empty(0, dtype=torch.float64, device="cuda")
+    Z = torch.empty((gm.n_species, 0), dtype=torch.float64, device="cuda")
+    pb = torch.full((gm.n_params, 3), 7.0, dtype=torch.float64, device="cuda")
+    pyro.production_rates_vjp(gm, e, e, Z, Z, params_bar=pb)
+    torch.cuda.synchronize()
+    assert bool((pb == 0).all())
+
+
+def test_vjp_full_size(lib_mechs):
+    """2^20 cells (the differentiation workload): finite results, sampled
+    cells against the oracle, and additivity of the parameter gradients over
+    a split of the cells."""
+    torch, pyro, gms = lib_mechs
+    m = mechs.load_config(1)
+    n = 1 << 20
+    T, p, Y, rho = states(2, n, m.S)
+    wbar = draw_cotangent(2, n, m.S)
+    announce(f"vjp full size n={n}")
+    r, t, y, wb = to_dev(torch, rho, T, Y, wbar)
+    Yb, Tb, pb = pyro.production_rates_vjp(gms[1], r, t, y, wb)
+    h = n // 2 + 37
+    _, _, p1 = pyro.production_rates_vjp(gms[1], r[:h], t[:h], y[:, :h], wb[:, :h])
+    _, _, p2 = pyro.production_rates_vjp(gms[1], r[h:], t[h:], y[:, h:].contiguous(),
+                                         wb[:, h:].contiguous())
+    torch.cuda.synchronize()
+    assert bool(torch.isfinite(Yb).all()) and bool(torch.isfinite(Tb).all())
+    assert bool(torch.isfinite(pb).all())
+    idx = np.array([0, 1, 63, 64, 12345, n // 2, n - 2, n - 1])
+    Ys = Yb[:, torch.from_numpy(idx).cuda()].cpu().numpy()
+    Ts = Tb[torch.from_numpy(idx).cuda()].cpu().numpy()
+    Yr, Tr, _ = gradients.vjp(m, rho[idx], T[idx], Y[:, idx], wbar[:, idx])
+    sY, sT, _ = _scales(m, rho[idx], T[idx], Y[:, idx], wbar[:, idx])
+    assert np.max(np.abs(Ys - Yr) / np.maximum(sY, 1e-300)) <= TOL
+    assert np.max(np.abs(Ts - Tr) / sT) <= TOL
+    sP_scale = np.abs(pb.cpu().numpy()) + np.abs(p1.cpu().numpy()) + np.abs(p2.cpu().numpy())
+    diff = np.abs((p1 + p2 - pb).cpu().numpy())
+    assert np.all(diff <= 1e-9 * sP_scale + 1e-300)
