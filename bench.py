@@ -1,15 +1,18 @@
 """Throughput of the per-cell thermochemistry hot path on one MI355X.
 
 One step runs the whole hot path over a batch of cells already resident in
-HBM: the Newton inversion T(e, Y) from a 1200 K guess, then the net
-production rates omega(rho, T, Y) at that temperature, on the 53-species,
-325-reaction synthetic mechanism (2^22 cells by default).  The figure of merit
+HBM: the Newton inversion T(e, Y) from a 1200 K guess, the net production
+rates omega(rho, T, Y) at that temperature, and the reverse-mode product of
+L = sum wbar omega (gradients with respect to Y, T and every Arrhenius
+triple), on the 53-species, 325-reaction synthetic mechanism (2^22 cells by
+default).  The figure of merit
 is million cells per second (higher is better).
 
-Prints one JSON line with, besides the throughput, a roofline entry for the
-production-rate kernel (algorithmic FP64 flops per launch over its average
-launch time, timed with HIP events on the stream it runs on) and the CPU
-oracle timed on a bounded sample of the same workload.
+Prints one JSON line with, besides the throughput, roofline entries for the
+production-rate and reverse-mode kernels (algorithmic FP64 flops per launch
+over the average launch time, timed with HIP events on the stream they run
+on; "roofline" is the kernel that takes longer) and the CPU oracle timed on a
+bounded sample of the same workload.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--cells N]
                        [--no-cpu-baseline] [--cpu-sample N]
@@ -42,37 +45,66 @@ def wdot_flops_per_cell(gm):
             + 2 * n_pd * gm.n_species + 128 * gm.n_falloff + 30)
 
 
+def vjp_flops_per_cell(gm):
+    """Algorithmic flops of the reverse sweep for one cell: the forward
+    recomputation plus 2 nnz for nu^T wbar, 15 per reaction for the local
+    adjoints, 4 nnz for the species sums, 6 per Arrhenius triple for the cell
+    sums, 2 n_pd S for the third-body contraction, 12 S for the enthalpy
+    terms and 150 per falloff reaction for the broadening-factor derivatives."""
+    S, R = gm.n_species, gm.n_reactions
+    nnz = gm.nnz_reactant + gm.nnz_product
+    n_pd = gm.n_third_body + gm.n_falloff
+    return (wdot_flops_per_cell(gm) + 2 * nnz + 15 * R + 4 * nnz + 6 * gm.n_params
+            + 2 * n_pd * S + 12 * S + 150 * gm.n_falloff)
+
+
+def vjp_bytes_per_cell(gm):
+    """Compulsory HBM bytes of the VJP per cell: read rho, T, Y, wbar; write
+    Ybar, Tbar."""
+    return 8 * (3 + 3 * gm.n_species)
+
+
 def wdot_bytes_per_cell(gm):
     """Compulsory HBM bytes of omega per cell: read rho, T, Y; write omega."""
     return 8 * (2 + 2 * gm.n_species)
 
 
-def cpu_baseline(n_sample, cfg=1):
-    """The oracle (NumPy, single thread for its elementwise work) on the first
-    ``n_sample`` cells of the same workload: Newton from 1200 K, then omega."""
+def cpu_baseline(n_fwd, n_vjp, cfg=1):
+    """The oracle (NumPy, one thread for its elementwise work) on the first
+    cells of the same workload: Newton from 1200 K and omega on ``n_fwd``
+    cells, the complex-step gradients on ``n_vjp`` cells; the per-cell times
+    add up to one step."""
     import numpy as np
-    from oracle import eos, kinetics, mechfile, newton, thermo
-    from pyro_synth.states import draw_states
+    from oracle import eos, gradients, kinetics, mechfile, newton, thermo
+    from pyro_synth.states import draw_cotangent, draw_states
     m = mechfile.load(MECH)
     chunk = 8192
-    elapsed = 0.0
+    t_fwd = 0.0
     done = 0
-    while done < n_sample:
-        k = min(chunk, n_sample - done)
+    while done < n_fwd:
+        k = min(chunk, n_fwd - done)
         T, p, Y = draw_states(cfg, k, m.S, first=done)
         rho = eos.density(m, p, T, Y)
         e = thermo.mixture_internal_energy(m, T, Y)
         t0 = time.perf_counter()
         Tn, st = newton.temperature(m, e, Y, 1200.0)
         w = kinetics.net_production_rates(m, rho, Tn, Y)
-        elapsed += time.perf_counter() - t0
+        t_fwd += time.perf_counter() - t0
         assert np.isfinite(w).all()
         done += k
-    return {"value": n_sample / elapsed / 1e6, "unit": "Mcells/s", "cores": 1,
+    T, p, Y = draw_states(cfg, n_vjp, m.S)
+    rho = eos.density(m, p, T, Y)
+    wbar = draw_cotangent(2, n_vjp, m.S)
+    t0 = time.perf_counter()
+    gradients.vjp(m, rho, T, Y, wbar)
+    t_vjp = time.perf_counter() - t0
+    per_cell = t_fwd / n_fwd + t_vjp / n_vjp
+    return {"value": round(1e-6 / per_cell, 6), "unit": "Mcells/s", "cores": 1,
             "kind": "oracle",
-            "sample": f"first {n_sample} cells of the 2^22-cell workload, Newton + omega, "
-                      f"NumPy oracle in chunks of {chunk} ({elapsed:.1f} s), "
-                      f"host {platform.processor() or platform.machine()}"}
+            "sample": f"first cells of the 2^22-cell workload: Newton + omega on {n_fwd} "
+                      f"cells ({t_fwd:.1f} s), complex-step VJP on {n_vjp} cells "
+                      f"({t_vjp:.1f} s); NumPy oracle, one thread; host "
+                      f"{platform.processor() or platform.machine()}"}
 
 
 def main():
@@ -82,7 +114,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cells", type=int, default=1 << 22)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=1 << 18)
+    ap.add_argument("--cpu-sample", type=int, default=1 << 19,
+                    help="cells for the oracle's Newton + omega (the VJP uses 1/64 of them)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -95,7 +128,7 @@ def main():
     import torch
 
     import paper_2503_24286_amd as pyro
-    from pyro_synth.states import draw_states
+    from pyro_synth.states import draw_cotangent, draw_states
 
     torch.cuda.set_device(0)
     gm = pyro.Mechanism(MECH)
@@ -110,20 +143,29 @@ def main():
     T_out = torch.empty_like(T_d)
     status = torch.empty(n, dtype=torch.int32, device="cuda")
     w = torch.empty_like(Y_d)
+    wbar = dev(draw_cotangent(2, n, gm.n_species))
+    Ybar = torch.empty_like(Y_d)
+    Tbar = torch.empty_like(T_d)
+    pbar = torch.empty((gm.n_params, 3), dtype=torch.float64, device="cuda")
     torch.cuda.synchronize()
     print(f"# inputs ready: {n} cells in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
 
     stream = torch.cuda.current_stream()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for _ in range(args.steps)]
+    def events():
+        return [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ev0, ev1, ev2 = events(), events(), events()
 
     def step(i=None):
         pyro.temperature(gm, e, Y_d, T_guess=1200.0, out=T_out, status=status)
         if i is not None:
-            ev[i][0].record(stream)
+            ev0[i].record(stream)
         pyro.production_rates(gm, rho, T_out, Y_d, out=w)
         if i is not None:
-            ev[i][1].record(stream)
+            ev1[i].record(stream)
+        pyro.production_rates_vjp(gm, rho, T_out, Y_d, wbar, Ybar=Ybar, Tbar=Tbar,
+                                  params_bar=pbar)
+        if i is not None:
+            ev2[i].record(stream)
 
     for _ in range(args.warmup):
         step()
@@ -136,14 +178,28 @@ def main():
     end.record(stream)
     torch.cuda.synchronize()
     total_ms = start.elapsed_time(end)
-    wdot_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    wdot_ms = float(np.mean([a.elapsed_time(b) for a, b in zip(ev0, ev1)]))
+    vjp_ms = float(np.mean([a.elapsed_time(b) for a, b in zip(ev1, ev2)]))
     if not bool(torch.isfinite(w).all()) or not bool((status > 0).all()):
         raise RuntimeError("non-finite rates or unconverged Newton in the benchmark")
+    if not bool(torch.isfinite(Ybar).all()) or not bool(torch.isfinite(pbar).all()):
+        raise RuntimeError("non-finite gradients in the benchmark")
 
     ms_per_step = total_ms / args.steps
     value = n / (ms_per_step * 1e-3) / 1e6
-    flops = wdot_flops_per_cell(gm) * n
-    achieved = flops / (wdot_ms * 1e-3) / 1e12
+
+    def roof(name, ms, fpc, bpc):
+        achieved = fpc * n / (ms * 1e-3) / 1e12
+        return {"kernel": name, "bound": "alu", "achieved": round(achieved, 3),
+                "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": None,
+                "flops_per_cell": fpc,
+                "hbm_GBps_compulsory": round(bpc * n / (ms * 1e-3) / 1e9, 1)}
+
+    roofs = {"wdot": roof("wdot_f64_kernel", wdot_ms, wdot_flops_per_cell(gm),
+                          wdot_bytes_per_cell(gm)),
+             "vjp": roof("vjp_kernel", vjp_ms, vjp_flops_per_cell(gm), vjp_bytes_per_cell(gm))}
+    dominant = "vjp" if vjp_ms >= wdot_ms else "wdot"
     result = {
         "metric": "Mcells/s for wdot (53sp/325rxn FP64) + VJP; surrogate vs exact at <=1e-3 rel err",
         "value": round(value, 3),
@@ -160,25 +216,17 @@ def main():
         "config": {
             "workload": f"53-species 325-reaction synthetic mechanism, {n} cells, "
                         "T U[300,3000] K, log10 p U[4,6.5], Y Dirichlet(0.3)",
-            "step": "newton T(e,Y) from 1200 K + wdot(rho,T,Y)",
+            "step": "newton T(e,Y) from 1200 K + wdot(rho,T,Y) + VJP of sum(wbar*wdot)",
             "n_cells": n, "species": gm.n_species, "reactions": gm.n_reactions,
         },
-        "kernels_ms": {"wdot": round(wdot_ms, 4), "newton_and_rest": round(ms_per_step - wdot_ms, 4)},
-        "roofline": {
-            "kernel": "wdot_f64_kernel",
-            "bound": "alu",
-            "achieved": round(achieved, 3),
-            "peak": PEAK_FP64_TFLOPS,
-            "unit": "TFLOP/s",
-            "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
-            "traffic": None,
-            "flops_per_cell": wdot_flops_per_cell(gm),
-            "hbm_GBps_compulsory": round(wdot_bytes_per_cell(gm) * n / (wdot_ms * 1e-3) / 1e9, 1),
-        },
+        "kernels_ms": {"wdot": round(wdot_ms, 4), "vjp": round(vjp_ms, 4),
+                       "newton_and_rest": round(ms_per_step - wdot_ms - vjp_ms, 4)},
+        "roofline": roofs[dominant],
+        "roofline_other": roofs["wdot" if dominant == "vjp" else "vjp"],
     }
     gm.close()
     if not args.no_cpu_baseline:
-        result["cpu_baseline"] = cpu_baseline(args.cpu_sample)
+        result["cpu_baseline"] = cpu_baseline(args.cpu_sample, max(args.cpu_sample // 64, 64))
     print(json.dumps(result), flush=True)
 
 
