@@ -14,12 +14,20 @@ over the average launch time, timed with HIP events on the stream they run
 on; "roofline" is the kernel that takes longer) and the CPU oracle timed on a
 bounded sample of the same workload.
 
+A second object, "surrogate", reports the learned surrogate on the same
+mechanism: its training on exact-kernel labels, and for each target error the
+calibrated thresholds, the fallback fraction, the error percentiles against
+the exact kernel and the speed against the exact kernel alone.
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--cells N]
-                       [--no-cpu-baseline] [--cpu-sample N]
+                       [--no-cpu-baseline] [--cpu-sample N] [--no-surrogate]
+                       [--train-states N] [--members E] [--hidden H]
+                       [--epochs K] [--batch B] [--lr LR] [--targets ...]
 """
 
 import argparse
 import json
+import math
 import os
 import platform
 import sys
@@ -107,6 +115,127 @@ def cpu_baseline(n_fwd, n_vjp, cfg=1):
                       f"{platform.processor() or platform.machine()}"}
 
 
+def _time_ms(fn, reps, stream):
+    """Average time of fn() over reps launches, timed with HIP events on
+    the stream the kernels run on."""
+    import torch
+    fn()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(reps):
+        fn()
+    b.record(stream)
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def surrogate_leg(args, log):
+    """Config-4 surrogate: train an ensemble on exact-kernel labels of
+    ``--train-states`` seeded states with the library's own BF16 kernels,
+    calibrate the fallback thresholds on 2^20 held-out states for each
+    target error, then evaluate on ``--cells`` fresh states with the exact
+    kernel as the judge of the error."""
+    import numpy as np
+    import torch
+
+    import paper_2503_24286_amd as pyro
+    from paper_2503_24286_amd import surrogate as sur
+    from pyro_synth.configs import SEEDS
+
+    gm = pyro.Mechanism(MECH)
+    stream = torch.cuda.current_stream()
+    S = gm.n_species
+    t0 = time.time()
+    data, norm = sur.build_dataset(gm, args.train_states, SEEDS["surrogate_train"],
+                                   threads=args.threads, log=log)
+    t_data = time.time() - t0
+    trainers, hist = [], []
+    t1 = time.time()
+    for e in range(args.members):
+        tr, h = sur.train_member(data, args.hidden, sur.INIT_SEED + e, args.epochs, args.batch,
+                                 lr=args.lr, log=log)
+        trainers.append(tr)
+        hist.append(h)
+    torch.cuda.synchronize()
+    t_train = time.time() - t1
+    del data
+    model = sur.Surrogate.from_trainers(trainers, norm)
+    del trainers
+    torch.cuda.empty_cache()
+
+    def draw(n, seed, cfg=4):
+        T = np.empty(n)
+        p = np.empty(n)
+        Y = np.empty((S, n))
+        for a, Tc, pc, Yc in sur.draw_chunks(cfg, n, S, seed, threads=args.threads):
+            T[a:a + Tc.shape[0]] = Tc
+            p[a:a + Tc.shape[0]] = pc
+            Y[:, a:a + Tc.shape[0]] = Yc
+        return T, p, Y
+
+    # calibration on held-out states, the exact kernel as the judge
+    Th, ph, Yh = draw(1 << 20, SEEDS["surrogate_heldout"])
+    Td, pd, Yd = (torch.from_numpy(x).cuda() for x in (Th, ph, Yh))
+    rho, w_ex = sur.label(gm, Td, pd, Yd)
+    w_s, _, _, ind = model.eval(gm, rho, Td, Yd, indicators=True)
+    err, d2, r2 = sur.cell_errors(w_s.cpu().numpy(), w_ex.cpu().numpy())
+    ind = ind.cpu().numpy()
+    held_out = {"p50": float(np.median(err)), "p99": float(np.percentile(err, 99)),
+                "p99.9": float(np.percentile(err, 99.9))}
+    thresholds = {t: sur.calibrate(ind[0], ind[1], err, d2, r2, target=t)
+                  for t in args.targets}
+    del Td, pd, Yd, rho, w_ex, w_s
+    log(f"surrogate: held-out errors {held_out}; thresholds {thresholds}")
+
+    # evaluation workload: fresh config-4 states
+    n = args.cells
+    Td, pd, Yd = (torch.from_numpy(x).cuda() for x in draw(n, SEEDS["states"] + 4))
+    rho = pyro.density(gm, pd, Td, Yd)
+    w_ex = pyro.production_rates(gm, rho, Td, Yd)
+    out = torch.empty_like(w_ex)
+    ms_exact = _time_ms(lambda: pyro.production_rates(gm, rho, Td, Yd, out=out), args.reps,
+                        stream)
+    ms_mlp = _time_ms(lambda: model.eval(gm, rho, Td, Yd, out=out), args.reps, stream)
+    ref_norm = torch.sqrt((w_ex * w_ex).sum(0))
+    r2_sum = float((ref_norm.double() ** 2).sum())
+    curve = []
+    for target in args.targets:
+        ts, tr, frac_cal = thresholds[target]
+        w_s, flags, count, _ = model.eval(gm, rho, Td, Yd, thr_spread=ts, thr_resid=tr, out=out)
+        d = torch.sqrt(((w_s - w_ex) ** 2).sum(0))
+        e = (d / ref_norm.clamp_min(1e-300)).cpu().numpy()
+        frob = math.sqrt(float((d.double() ** 2).sum()) / r2_sum)
+        frac = int(count.item()) / n
+        ms = _time_ms(lambda: model.eval(gm, rho, Td, Yd, thr_spread=ts, thr_resid=tr, out=out),
+                      args.reps, stream)
+        row = {"target": target, "thr_spread": ts, "thr_resid": tr,
+               "fallback_fraction": round(frac, 5), "fallback_fraction_heldout": round(frac_cal, 5),
+               "ms": round(ms, 4), "Mcells_s": round(n / ms / 1e3, 3),
+               "gain_vs_exact": round(ms_exact / ms, 4),
+               "err": {"p50": float(np.percentile(e, 50)), "p99": float(np.percentile(e, 99)),
+                       "p99.9": float(np.percentile(e, 99.9)), "max": float(e.max()),
+                       "frobenius": frob}}
+        curve.append(row)
+        log(f"surrogate: target {target}: fallback {frac:.4f}, {ms:.3f} ms, "
+            f"gain {ms_exact / ms:.3f}")
+    main_row = curve[0]
+    gm.close()
+    return {
+        "workload": f"53-species mechanism; ensemble of {args.members} MLPs 64(56 used)-"
+                    f"{args.hidden}-{args.hidden}-{args.hidden}-64(53 used), SiLU, BF16 "
+                    f"weights/activations, FP32 accumulation; trained on {args.train_states} "
+                    f"exact-kernel states, evaluated on {n} fresh states",
+        "train": {"states": args.train_states, "epochs": args.epochs, "batch": args.batch,
+                  "lr": args.lr, "data_s": round(t_data, 2), "train_s": round(t_train, 2),
+                  "mse_by_epoch": [[round(x, 6) for x in h] for h in hist]},
+        "heldout_err_without_fallback": held_out,
+        "exact_ms": round(ms_exact, 4), "exact_Mcells_s": round(n / ms_exact / 1e3, 3),
+        "mlp_only_ms": round(ms_mlp, 4), "mlp_only_Mcells_s": round(n / ms_mlp / 1e3, 3),
+        "at_1e-3": main_row, "curve": curve,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -116,6 +245,16 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=1 << 19,
                     help="cells for the oracle's Newton + omega (the VJP uses 1/64 of them)")
+    ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--train-states", type=int, default=1 << 24)
+    ap.add_argument("--members", type=int, default=2)
+    ap.add_argument("--hidden", type=int, default=256)
+    ap.add_argument("--epochs", type=int, default=8)
+    ap.add_argument("--batch", type=int, default=8192)
+    ap.add_argument("--lr", type=float, default=2e-3)
+    ap.add_argument("--reps", type=int, default=10)
+    ap.add_argument("--threads", type=int, default=16)
+    ap.add_argument("--targets", type=float, nargs="+", default=[1e-3, 1e-2, 1e-1])
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -225,6 +364,12 @@ def main():
         "roofline_other": roofs["wdot" if dominant == "vjp" else "vjp"],
     }
     gm.close()
+    del T_d, p_d, Y_d, rho, e, T_out, status, w, wbar, Ybar, Tbar, pbar
+    torch.cuda.empty_cache()
+    if not args.no_surrogate:
+        def log(msg):
+            print(f"# {msg}", file=sys.stderr, flush=True)
+        result["surrogate"] = surrogate_leg(args, log)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(args.cpu_sample, max(args.cpu_sample // 64, 64))
     print(json.dumps(result), flush=True)

@@ -183,6 +183,102 @@ PYRO_API int pyro_internal_energy(const pyro_mech* mech, int64_t n, int64_t ld,
                          const double* T, const double* Y, double* e_out,
                          void* stream);
 
+/*
+ * Learned surrogate of the net production rates
+ * ----------------------------------------------
+ * Not part of the paper's method: an MLP that maps per-cell features to
+ * omega, trained on states the exact kernel labels, with per-cell fallback
+ * to the exact kernel where its error indicators trip.  BF16 weights and
+ * activations, FP32 accumulation (v_mfma_f32_32x32x16_bf16).  BF16 values
+ * are passed as raw 16-bit patterns (uint16_t).
+ *
+ * Network: 64 -> H -> H -> H -> 64 (SiLU after the three hidden layers).
+ * Features (row of 64 per cell, see pyro_surrogate_features): T/1000,
+ * log10 p, ln(max(Y_k, 0) + 1e-12) for the S species, shifted and scaled,
+ * then a constant 1 and zeros.  Outputs: z_k = (asinh(omega_k/s_k) - mu_k)
+ * / sigma_k in the first S columns.  One member's parameters are packed:
+ * weights W1 [64][H], W2 [H][H], W3 [H][H], W4 [H][64] (row-major, input
+ * index first), biases b1 [H], b2 [H], b3 [H], b4 [64].
+ */
+typedef struct pyro_surrogate {
+    int32_t n_members;            /* ensemble size E, 1..4                    */
+    int32_t hidden;               /* H, a multiple of 64                      */
+    const uint16_t* weights;      /* device, E packed weight sets (BF16)      */
+    const float* biases;          /* device, E packed bias sets               */
+    const float* feat_shift;      /* device [64]                              */
+    const float* feat_scale;      /* device [64]                              */
+    const double* target_scale;   /* device [S]: s_k                          */
+    const double* target_mean;    /* device [S]: mu_k                         */
+    const double* target_std;     /* device [S]: sigma_k                      */
+} pyro_surrogate;
+
+/* Number of packed weights and biases of one member; returns the weights
+ * count, 0 for an invalid hidden width. */
+PYRO_API size_t pyro_mlp_param_counts(int hidden, int64_t* n_weights, int64_t* n_biases);
+
+/* Forward pass of one member on a batch: X [batch][64] BF16 features,
+ * acts a BF16 buffer of 6*batch*H receiving (pre-activation, activation) of
+ * the three hidden layers, Z [batch][64] FP32 outputs. */
+PYRO_API int pyro_mlp_forward(int hidden, int64_t batch, const uint16_t* X,
+                              const uint16_t* W, const float* b, uint16_t* acts,
+                              float* Z, void* stream);
+
+/* Backward pass from dZ [batch][64] (BF16): gW and gb (FP32, packed like
+ * the parameters) receive dLoss/dW and dLoss/db, summed over the batch in a
+ * fixed order.  work: BF16 buffer of 2*batch*H; split_work: FP32 buffer of
+ * splits*H*H (the batch is split into `splits` ranges for the weight
+ * gradients). */
+PYRO_API int pyro_mlp_backward(int hidden, int64_t batch, const uint16_t* X,
+                               const uint16_t* W, const uint16_t* acts,
+                               const uint16_t* dZ, float* gW, float* gb,
+                               uint16_t* work, float* split_work, int splits,
+                               void* stream);
+
+/* Mean squared error over the first n_out of 64 output columns:
+ * dZ = 2 (Z - Zt)/(batch n_out) (BF16) and per-block partial sums of the
+ * squared errors in loss_partials[pyro_mlp_loss_partials(batch)]. */
+PYRO_API int64_t pyro_mlp_loss_partials(int64_t batch);
+PYRO_API int pyro_mlp_mse(int64_t batch, int n_out, const float* Z, const float* Zt,
+                          uint16_t* dZ, float* loss_partials, void* stream);
+
+/* AdamW with decoupled weight decay on FP32 master weights w (step >= 1);
+ * w_bf16, if not NULL, receives the rounded copy. */
+PYRO_API int pyro_adamw_step(int64_t n, float* w, uint16_t* w_bf16, const float* grad,
+                             float* m1, float* m2, float lr, float beta1, float beta2,
+                             float eps, float weight_decay, int step, void* stream);
+PYRO_API int pyro_to_bf16(int64_t n, const float* x, uint16_t* y, void* stream);
+
+/* Features X [n][64] (BF16) of the cells (rho, T, Y as for
+ * pyro_production_rates); shift and scale are device [64] FP32. */
+PYRO_API int pyro_surrogate_features(const pyro_mech* mech, int64_t n, int64_t ld,
+                                     const double* rho, const double* T, const double* Y,
+                                     const float* shift, const float* scale, uint16_t* X,
+                                     void* stream);
+/* Training targets Zt [n][64] (FP32) from omega [S*ld]. */
+PYRO_API int pyro_surrogate_targets(const pyro_mech* mech, int64_t n, int64_t ld,
+                                    const double* wdot, const double* scale,
+                                    const double* mean, const double* std_dev, float* Zt,
+                                    void* stream);
+
+/* Bytes of device workspace pyro_surrogate_eval needs for n cells. */
+PYRO_API size_t pyro_surrogate_workspace_size(const pyro_mech* mech, int64_t n, int hidden,
+                                              int members);
+/*
+ * Surrogate evaluation with fallback: wdot [S*ld] receives the ensemble-mean
+ * prediction, then the exact production rates for every cell that is not
+ * kept: a cell is kept only if its prediction is finite, its ensemble spread
+ * is below thr_spread and its element residual below thr_resid (strictly).  fell_back[n] (device u8) marks those
+ * cells, *n_fallback (device int64) counts them; indicators, if not NULL,
+ * receives the spread [n] then the residual [n].  thr = 0 sends every cell
+ * to the exact kernel, +inf none.
+ */
+PYRO_API int pyro_surrogate_eval(const pyro_mech* mech, const pyro_surrogate* sur,
+                                 int64_t n, int64_t ld, const double* rho, const double* T,
+                                 const double* Y, double thr_spread, double thr_resid,
+                                 double* wdot, uint8_t* fell_back, int64_t* n_fallback,
+                                 double* indicators, void* workspace, size_t workspace_bytes,
+                                 void* stream);
+
 #ifdef __cplusplus
 }
 #endif

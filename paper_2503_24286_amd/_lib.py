@@ -57,6 +57,31 @@ SIGNATURES = {
     "pyro_internal_energy": (_I, [_P, _I64, _I64, _P, _P, _P, _P]),
 }
 
+class Surrogate(ctypes.Structure):
+    _fields_ = [("n_members", ctypes.c_int32), ("hidden", ctypes.c_int32),
+                ("weights", ctypes.c_void_p), ("biases", ctypes.c_void_p),
+                ("feat_shift", ctypes.c_void_p), ("feat_scale", ctypes.c_void_p),
+                ("target_scale", ctypes.c_void_p), ("target_mean", ctypes.c_void_p),
+                ("target_std", ctypes.c_void_p)]
+
+
+_SZ = ctypes.c_size_t
+_F = ctypes.c_float
+SIGNATURES.update({
+    "pyro_mlp_param_counts": (_SZ, [_I, ctypes.POINTER(_I64), ctypes.POINTER(_I64)]),
+    "pyro_mlp_forward": (_I, [_I, _I64, _P, _P, _P, _P, _P, _P]),
+    "pyro_mlp_backward": (_I, [_I, _I64, _P, _P, _P, _P, _P, _P, _P, _P, _I, _P]),
+    "pyro_mlp_loss_partials": (_I64, [_I64]),
+    "pyro_mlp_mse": (_I, [_I64, _I, _P, _P, _P, _P, _P]),
+    "pyro_adamw_step": (_I, [_I64, _P, _P, _P, _P, _P, _F, _F, _F, _F, _F, _I, _P]),
+    "pyro_to_bf16": (_I, [_I64, _P, _P, _P]),
+    "pyro_surrogate_features": (_I, [_P, _I64, _I64, _P, _P, _P, _P, _P, _P, _P]),
+    "pyro_surrogate_targets": (_I, [_P, _I64, _I64, _P, _P, _P, _P, _P, _P]),
+    "pyro_surrogate_workspace_size": (_SZ, [_P, _I64, _I, _I]),
+    "pyro_surrogate_eval": (_I, [_P, ctypes.POINTER(Surrogate), _I64, _I64, _P, _P, _P, _D, _D,
+                                 _P, _P, _P, _P, _P, _SZ, _P]),
+})
+
 _lib = None
 
 

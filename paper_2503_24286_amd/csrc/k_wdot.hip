@@ -140,8 +140,13 @@ template <int MAXOWN, int MAXPD>
 __global__ __launch_bounds__(kWaves * 64) void wdot_f64_kernel(
     DevMech m, int64_t n, int64_t ld, const double* __restrict__ rho,
     const double* __restrict__ T, const double* __restrict__ Y,
-    double* __restrict__ wdot, const double* __restrict__ params) {
+    double* __restrict__ wdot, const double* __restrict__ params,
+    const int64_t* __restrict__ n_dev) {
     extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
+    if (n_dev) {
+        n = *n_dev;  // cells counted on the device (the whole workgroup agrees)
+        if (int64_t(blockIdx.x) * kTile >= n) return;
+    }
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t cell = int64_t(blockIdx.x) * kTile + lane;
@@ -259,12 +264,12 @@ __global__ __launch_bounds__(kWaves * 64) void wdot_f64_kernel(
 template <int MAXOWN, int MAXPD>
 hipError_t launch_f64(const pyro_mech* m, int64_t n, int64_t ld, const double* rho,
                       const double* T, const double* Y, double* wdot,
-                      const double* params, hipStream_t stream) {
+                      const double* params, hipStream_t stream, const int64_t* n_dev) {
     const size_t lds = production_rates_lds_bytes(m);
     const int64_t blocks = (n + kTile - 1) / kTile;
     hipLaunchKernelGGL((wdot_f64_kernel<MAXOWN, MAXPD>), dim3(unsigned(blocks)),
                        dim3(kWaves * 64), lds, stream, m->dev, n, ld, rho, T, Y, wdot,
-                       params ? params : m->dev.params);
+                       params ? params : m->dev.params, n_dev);
     return hipGetLastError();
 }
 
@@ -278,11 +283,11 @@ hipError_t set_lds(int bytes) {
 template <int MAXPD>
 hipError_t dispatch_own(const pyro_mech* m, int64_t n, int64_t ld, const double* r,
                         const double* t, const double* y, double* o, const double* params,
-                        hipStream_t stream) {
-    if (m->max_own <= 8) return launch_f64<8, MAXPD>(m, n, ld, r, t, y, o, params, stream);
-    if (m->max_own <= 16) return launch_f64<16, MAXPD>(m, n, ld, r, t, y, o, params, stream);
-    if (m->max_own <= 32) return launch_f64<32, MAXPD>(m, n, ld, r, t, y, o, params, stream);
-    return launch_f64<64, MAXPD>(m, n, ld, r, t, y, o, params, stream);
+                        hipStream_t stream, const int64_t* nd) {
+    if (m->max_own <= 8) return launch_f64<8, MAXPD>(m, n, ld, r, t, y, o, params, stream, nd);
+    if (m->max_own <= 16) return launch_f64<16, MAXPD>(m, n, ld, r, t, y, o, params, stream, nd);
+    if (m->max_own <= 32) return launch_f64<32, MAXPD>(m, n, ld, r, t, y, o, params, stream, nd);
+    return launch_f64<64, MAXPD>(m, n, ld, r, t, y, o, params, stream, nd);
 }
 
 }  // namespace
@@ -304,14 +309,15 @@ hipError_t prepare_production_rates(const pyro_mech* m) {
 
 hipError_t launch_production_rates(const pyro_mech* m, int64_t n, int64_t ld, int dtype,
                                    const void* rho, const void* T, const void* Y,
-                                   void* wdot, const double* params, hipStream_t stream) {
+                                   void* wdot, const double* params, hipStream_t stream,
+                                   const int64_t* n_dev) {
     (void)dtype;
     const double* r = static_cast<const double*>(rho);
     const double* t = static_cast<const double*>(T);
     const double* y = static_cast<const double*>(Y);
     double* o = static_cast<double*>(wdot);
-    if (m->max_pdw <= 8) return dispatch_own<8>(m, n, ld, r, t, y, o, params, stream);
-    return dispatch_own<16>(m, n, ld, r, t, y, o, params, stream);
+    if (m->max_pdw <= 8) return dispatch_own<8>(m, n, ld, r, t, y, o, params, stream, n_dev);
+    return dispatch_own<16>(m, n, ld, r, t, y, o, params, stream, n_dev);
 }
 
 }  // namespace pyro

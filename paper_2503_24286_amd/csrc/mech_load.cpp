@@ -361,6 +361,8 @@ int load_mechanism(const char* path, pyro_mech** out) {
     std::vector<int32_t> chunk_fo(std::max(n_chunks, 1), 0);
     for (int j = 0; j < R; ++j)
         if (f.rtype[j] >= 2) chunk_fo[chunk_of[j]] = 1;
+    std::vector<double> comp_d(f.comp.begin(), f.comp.end());
+    if (comp_d.empty()) comp_d.push_back(0.0);
     std::vector<double> eff_t(size_t(S) * std::max(n_pd, 1), 0.0);
     for (int i = 0; i < n_pd; ++i)
         for (int k = 0; k < S; ++k) eff_t[size_t(k) * std::max(n_pd, 1) + i] = f.eff[size_t(i) * S + k];
@@ -450,6 +452,7 @@ int load_mechanism(const char* path, pyro_mech** out) {
         {vgent.data(), vgent.size() * sizeof(uint32_t), 0},
         {eff_t.data(), eff_t.size() * sizeof(double), 0},
         {chunk_fo.data(), chunk_fo.size() * sizeof(int32_t), 0},
+        {comp_d.data(), comp_d.size() * sizeof(double), 0},
     };
     size_t total = 0;
     for (auto& p : parts) {
@@ -506,6 +509,8 @@ int load_mechanism(const char* path, pyro_mech** out) {
     d.vgent = reinterpret_cast<const uint32_t*>(base + parts[13].off);
     d.eff_t = reinterpret_cast<const double*>(base + parts[14].off);
     d.chunk_fo = reinterpret_cast<const int32_t*>(base + parts[15].off);
+    d.E = int(f.E);
+    d.comp = reinterpret_cast<const double*>(base + parts[16].off);
     err = prepare_production_rates(m);
     if (err == hipSuccess) err = prepare_vjp(m);
     if (err != hipSuccess) {

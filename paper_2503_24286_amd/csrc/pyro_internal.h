@@ -117,6 +117,10 @@ struct DevMech {
     const uint32_t* vgent;               // slot offset | nu' << 16 | nu'' << 24
     const double* eff_t;                 // [S][n_pd] efficiencies by species
     const int32_t* chunk_fo;             // [n_chunks] 1 if the chunk holds a falloff reaction
+    // surrogate
+    int32_t E;                           // elements
+    int32_t pad2;
+    const double* comp;                  // [E][S] atoms of element e in species k
 };
 
 }  // namespace pyro
@@ -147,10 +151,13 @@ int hip_fail(hipError_t err, const char* what);
 int load_mechanism(const char* path, pyro_mech** out);
 
 // Launchers (arguments already validated).
+// n_dev: optional device-resident cell count (<= n) read by the kernel; the
+// launch covers n cells and tiles past *n_dev exit at once.
 hipError_t launch_production_rates(const pyro_mech* m, int64_t n, int64_t ld,
                                    int dtype, const void* rho, const void* T,
                                    const void* Y, void* wdot,
-                                   const double* params, hipStream_t stream);
+                                   const double* params, hipStream_t stream,
+                                   const int64_t* n_dev = nullptr);
 hipError_t launch_temperature(const pyro_mech* m, int64_t n, int64_t ld,
                               const double* e, const double* Y,
                               const double* T_guess, double T_guess_value,

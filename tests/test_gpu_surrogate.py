@@ -1,0 +1,416 @@
+"""The learned surrogate's kernels against the oracle's MLP reference, and the
+evaluation pipeline's fallback contract, through the C ABI.
+
+GEMM checks are layer-isolated: the oracle recomputes each layer in FP64 from
+the BF16 operands the GPU itself used, so one rounding flip upstream cannot
+hide or excuse an error downstream.  With FP32 accumulation over K terms an
+FP32 result lies within ~K 2^-24 sum|a b| of the exact sum; the tests allow
+1e-5 sqrt(K) of that scale.  A BF16-rounded result may sit one BF16 step
+(2^-8 relative) from the rounding of the exact value.
+"""
+
+import ctypes
+import math
+
+import numpy as np
+import pytest
+
+import mechs
+from gpu_util import announce, states, to_dev, torch_cuda
+from oracle import kinetics
+from oracle import mlp as ref
+
+pytestmark = pytest.mark.gpu
+
+BF16_STEP = 2.0 ** -8
+
+
+@pytest.fixture(scope="module")
+def env():
+    torch = torch_cuda()
+    import paper_2503_24286_amd as pyro
+    from paper_2503_24286_amd import _lib, surrogate
+    gms = {c: pyro.Mechanism(mechs.config_path(c)) for c in (0, 1)}
+    yield torch, pyro, _lib, surrogate, gms
+    for m in gms.values():
+        m.close()
+
+
+def _p(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _s(torch):
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _bits(torch, a):
+    """BF16 bits of a float array as a device int16 tensor."""
+    return torch.from_numpy(ref.bf16_bits(a).view(np.int16).copy()).cuda()
+
+
+def _host_bf16(t):
+    return ref.from_bf16_bits(t.cpu().numpy().view(np.uint16))
+
+
+def _random_member(hidden, n_in, seed):
+    rng = np.random.default_rng(seed)
+    Ws, bs = [], []
+    for l, (k, n) in enumerate(ref.layer_dims(hidden)):
+        w = ref.bf16_round(rng.standard_normal((k, n)) * math.sqrt(2.0 / (n_in if l == 0 else k)))
+        if l == 0:
+            w[n_in:] = 0.0
+        Ws.append(w)
+        bs.append(rng.standard_normal(n).astype(np.float32).astype(np.float64) * 0.1)
+    return Ws, bs
+
+
+def _features(rng, batch, n_in):
+    X = np.zeros((batch, ref.FEAT_PAD))
+    X[:, :n_in] = rng.standard_normal((batch, n_in))
+    X[:, n_in] = 1.0
+    return ref.bf16_round(X)
+
+
+def _assert_fp32_sum(got, exact, scale, K, what):
+    tol = 1e-5 * math.sqrt(K) * scale + 1e-30
+    bad = np.abs(got - exact) > tol
+    assert not bad.any(), f"{what}: {bad.sum()} entries off, max {np.abs(got - exact).max():.3e}"
+
+
+def _assert_bf16_of(got, exact, scale, K, what):
+    """got is a BF16 rounding of a value within the FP32-sum bound of exact."""
+    tol = BF16_STEP * np.abs(exact) + 1e-5 * math.sqrt(K) * scale + 1e-30
+    bad = np.abs(got - exact) > tol
+    assert not bad.any(), f"{what}: {bad.sum()} entries off, max {np.abs(got - exact).max():.3e}"
+
+
+def _forward(torch, lib, hidden, X, Ws, bs):
+    B = X.shape[0]
+    w = np.concatenate([W.ravel() for W in Ws])
+    b = np.concatenate(bs).astype(np.float32)
+    Xd, Wd = _bits(torch, X), _bits(torch, w)
+    bd = torch.from_numpy(b).cuda()
+    acts = torch.empty(6 * B * hidden, dtype=torch.int16, device="cuda")
+    Z = torch.empty((B, ref.OUT_PAD), dtype=torch.float32, device="cuda")
+    rc = lib.pyro_mlp_forward(hidden, B, _p(Xd), _p(Wd), _p(bd), _p(acts), _p(Z), _s(torch))
+    assert rc == 0
+    torch.cuda.synchronize()
+    a = _host_bf16(acts).reshape(6, B, hidden)
+    P = [a[2 * l] for l in range(3)]
+    H = [a[2 * l + 1] for l in range(3)]
+    return (Xd, Wd, bd, acts), P, H, Z.cpu().numpy().astype(np.float64)
+
+
+@pytest.mark.parametrize("hidden,batch", [(64, 64), (128, 200), (256, 1000), (256, 4096 + 33)])
+def test_mlp_forward_layers_match_oracle(env, hidden, batch):
+    torch, pyro, _lib, sur, gms = env
+    lib = _lib.lib()
+    rng = np.random.default_rng(hidden + batch)
+    n_in = 56
+    X = _features(rng, batch, n_in)
+    Ws, bs = _random_member(hidden, n_in, 7)
+    announce(f"mlp forward H={hidden} B={batch}")
+    _, P, H, Z = _forward(torch, lib, hidden, X, Ws, bs)
+    a = X
+    for l in range(3):
+        exact = a @ Ws[l] + bs[l]
+        scale = np.abs(a) @ np.abs(Ws[l]) + np.abs(bs[l])
+        _assert_bf16_of(P[l], exact, scale, Ws[l].shape[0], f"P{l}")
+        # activation: BF16 rounding of silu of the GPU's own FP32 pre-activation,
+        # checked against silu of the exact sum (silu' is bounded by 1.1)
+        _assert_bf16_of(H[l], ref.silu(exact), 1.1 * scale, Ws[l].shape[0], f"H{l}")
+        a = H[l]
+    exact = a @ Ws[3] + bs[3]
+    scale = np.abs(a) @ np.abs(Ws[3]) + np.abs(bs[3])
+    _assert_fp32_sum(Z, exact, scale, Ws[3].shape[0], "Z")
+
+
+def test_mlp_forward_agrees_with_oracle_chain(env):
+    """The end-to-end forward against the oracle's own BF16 chain: per-layer
+    rounding flips leave the outputs close, not equal."""
+    torch, pyro, _lib, sur, gms = env
+    rng = np.random.default_rng(5)
+    X = _features(rng, 512, 56)
+    Ws, bs = _random_member(128, 56, 9)
+    _, P, H, Z = _forward(torch, _lib.lib(), 128, X, Ws, bs)
+    _, _, Zr = ref.forward(X, Ws, bs)
+    assert np.abs(Z - Zr).max() <= 0.02 * np.abs(Zr).max()
+
+
+def _backward(torch, lib, hidden, B, dev, dZ_bits, splits):
+    Xd, Wd, bd, acts = dev
+    nw = sum(k * n for k, n in ref.layer_dims(hidden))
+    nb = sum(n for _, n in ref.layer_dims(hidden))
+    gW = torch.empty(nw, dtype=torch.float32, device="cuda")
+    gb = torch.empty(nb, dtype=torch.float32, device="cuda")
+    work = torch.empty(2 * B * hidden, dtype=torch.int16, device="cuda")
+    split = torch.empty(splits * hidden * hidden, dtype=torch.float32, device="cuda")
+    rc = lib.pyro_mlp_backward(hidden, B, _p(Xd), _p(Wd), _p(acts), _p(dZ_bits), _p(gW), _p(gb),
+                               _p(work), _p(split), splits, _s(torch))
+    assert rc == 0
+    torch.cuda.synchronize()
+    gWs, gbs = ref.unpack(hidden, gW.cpu().numpy(), gb.cpu().numpy())
+    wk = _host_bf16(work).reshape(2, B, hidden)
+    return gWs, gbs, wk
+
+
+@pytest.mark.parametrize("hidden,batch,splits", [(64, 64, 1), (128, 300, 3), (256, 2048, 8),
+                                                 (256, 1000, 64)])
+def test_mlp_backward_layers_match_oracle(env, hidden, batch, splits):
+    torch, pyro, _lib, sur, gms = env
+    lib = _lib.lib()
+    rng = np.random.default_rng(100 + hidden + batch)
+    n_in = 56
+    X = _features(rng, batch, n_in)
+    Ws, bs = _random_member(hidden, n_in, 11)
+    announce(f"mlp backward H={hidden} B={batch} splits={splits}")
+    dev, P, H, Z = _forward(torch, lib, hidden, X, Ws, bs)
+    dZ = np.zeros((batch, ref.OUT_PAD))
+    dZ[:, :53] = ref.bf16_round(rng.standard_normal((batch, 53)) * 1e-3)
+    gW, gb, wk = _backward(torch, lib, hidden, batch, dev, _bits(torch, dZ), splits)
+    # the work buffers end with dP1 in the first half and dP0 in the second
+    dP = {1: wk[0], 0: wk[1]}
+    ins = [X, H[0], H[1], H[2]]
+    # layer 3 from dZ, layers 1 and 0 from the GPU's own dP: weight and bias
+    # gradients are FP32 sums over the batch
+    for l, dY in ((3, dZ), (1, dP[1]), (0, dP[0])):
+        _assert_fp32_sum(gW[l], ins[l].T @ dY, np.abs(ins[l]).T @ np.abs(dY), batch, f"gW{l}")
+        _assert_fp32_sum(gb[l], dY.sum(axis=0), np.abs(dY).sum(axis=0), batch, f"gb{l}")
+    # dP0 from dP1 through W1^T and silu'(P0)
+    exact = (dP[1] @ Ws[1].T) * ref.dsilu(P[0])
+    scale = (np.abs(dP[1]) @ np.abs(Ws[1].T)) * np.abs(ref.dsilu(P[0]))
+    _assert_bf16_of(dP[0], exact, scale, hidden, "dP0")
+    # layer 2 (its dP2 is not kept): against the oracle chain from dZ, where
+    # rounding flips in dP2 allow a few BF16 steps of the summed scale
+    dP2 = ref.bf16_round((dZ @ Ws[3].T) * ref.dsilu(P[2]))
+    exact = H[1].T @ dP2
+    scale = np.abs(H[1]).T @ np.abs(dP2)
+    assert np.all(np.abs(gW[2] - exact) <= 4 * BF16_STEP * scale + 1e-30)
+    dP1 = ref.bf16_round((dP2 @ Ws[2].T) * ref.dsilu(P[1]))
+    flips = np.abs(dP1 - dP[1]) > BF16_STEP * np.abs(dP1) * 1.01
+    assert flips.mean() < 0.01
+
+
+def test_mse_and_adamw_match_oracle(env):
+    torch, pyro, _lib, sur, gms = env
+    lib = _lib.lib()
+    rng = np.random.default_rng(3)
+    B, n_out = 777, 53
+    Z = rng.standard_normal((B, 64)).astype(np.float32)
+    Zt = rng.standard_normal((B, 64)).astype(np.float32)
+    Zd, Ztd = to_dev(torch, Z, Zt)
+    dZ = torch.empty((B, 64), dtype=torch.int16, device="cuda")
+    npart = lib.pyro_mlp_loss_partials(B)
+    part = torch.empty(npart, dtype=torch.float32, device="cuda")
+    announce("mse")
+    assert lib.pyro_mlp_mse(B, n_out, _p(Zd), _p(Ztd), _p(dZ), _p(part), _s(torch)) == 0
+    torch.cuda.synchronize()
+    loss, dref = ref.mse_grad(Z.astype(np.float64), Zt.astype(np.float64), n_out)
+    got = _host_bf16(dZ)
+    assert np.all(got[:, n_out:] == 0.0)
+    _assert_bf16_of(got, ref.mse_grad(Z.astype(np.float64), Zt.astype(np.float64), n_out,
+                                      rnd=lambda x: x)[1], np.abs(got) + 1e-30, 1, "dZ")
+    assert abs(float(part.double().sum()) - loss) <= 1e-5 * loss
+
+    n = 10000
+    w = rng.standard_normal(n).astype(np.float32)
+    g = rng.standard_normal(n).astype(np.float32)
+    m1 = (rng.standard_normal(n) * 0.1).astype(np.float32)
+    m2 = (rng.random(n) * 0.01).astype(np.float32)
+    wd, gd, m1d, m2d = to_dev(torch, w, g, m1, m2)
+    w16 = torch.empty(n, dtype=torch.int16, device="cuda")
+    announce("adamw")
+    assert lib.pyro_adamw_step(n, _p(wd), _p(w16), _p(gd), _p(m1d), _p(m2d), 1e-3, 0.9, 0.999,
+                               1e-8, 1e-2, 7, _s(torch)) == 0
+    torch.cuda.synchronize()
+    wr, m1r, m2r = ref.adamw(w.astype(np.float64), g.astype(np.float64), m1.astype(np.float64),
+                             m2.astype(np.float64), 1e-3, 0.9, 0.999, 1e-8, 1e-2, 7)
+    wg = wd.cpu().numpy().astype(np.float64)
+    assert np.allclose(m1d.cpu().numpy(), m1r, rtol=1e-6, atol=1e-9)
+    assert np.allclose(m2d.cpu().numpy(), m2r, rtol=1e-6, atol=1e-12)
+    assert np.allclose(wg, wr, rtol=1e-6, atol=1e-8)
+    # the BF16 copy is the rounding of the GPU's own FP32 weights
+    assert np.array_equal(w16.cpu().numpy().view(np.uint16), ref.bf16_bits(wg))
+
+
+@pytest.mark.parametrize("cfg,n", [(0, 300), (1, 1000)])
+def test_features_and_targets_match_oracle(env, cfg, n):
+    torch, pyro, _lib, sur, gms = env
+    m = mechs.load_config(cfg)
+    gm = gms[cfg]
+    T, p, Y, rho = states(4 if cfg == 1 else 0, n, m.S)
+    Y[0, :5] = 0.0                         # zero mass fractions hit the floor
+    rng = np.random.default_rng(8)
+    shift = np.zeros(64, np.float32)
+    scale = np.ones(64, np.float32)
+    shift[:m.S + 2] = rng.standard_normal(m.S + 2)
+    scale[:m.S + 2] = 0.2 + rng.random(m.S + 2)
+    r, t, y, sh, sc = to_dev(torch, rho, T, Y, shift, scale)
+    announce(f"features cfg{cfg} n={n}")
+    X = sur.features(gm, r, t, y, sh, sc)
+    torch.cuda.synchronize()
+    got = _host_bf16(X)
+    exact = ref.features(m, rho, T, Y, shift.astype(np.float64), scale.astype(np.float64))
+    _assert_bf16_of(got, exact, np.abs(exact), 1, "features")
+    assert np.all(got[:, m.S + 3:] == 0.0) and np.all(got[:, m.S + 2] == 1.0)
+
+    w = kinetics.net_production_rates(m, rho, T, Y)
+    s = np.median(np.abs(w), axis=1) + 1.0
+    mu = rng.standard_normal(m.S)
+    sig = 0.5 + rng.random(m.S)
+    wd, sd, mud, sgd = to_dev(torch, w, s, mu, sig)
+    Zt = sur.targets(gm, wd, sd, mud, sgd)
+    torch.cuda.synchronize()
+    zr = ref.targets(w, s, mu, sig)
+    assert np.allclose(Zt.cpu().numpy(), zr, rtol=2e-7, atol=1e-6)
+
+
+def _trained_like_surrogate(sur, m, hidden=128, members=2, seed=21):
+    """A surrogate with random weights and normalisation statistics of the
+    right scale (the pipeline's contract does not depend on training)."""
+    ws, bs = [], []
+    for e in range(members):
+        w, b = sur.init_member(hidden, m.S + 3, m.S, seed + e)
+        ws.append(ref.bf16_bits(w))
+        bs.append(b)
+    S = m.S
+    shift = np.zeros(64, np.float32)
+    scale = np.ones(64, np.float32)
+    shift[2:S + 2] = -10.0
+    scale[2:S + 2] = 0.2
+    shift[0] = 1.6
+    norm = sur.Normalisation(shift, scale, np.full(S, 10.0), np.zeros(S), np.full(S, 3.0))
+    return sur.Surrogate(hidden, np.stack(ws), np.stack(bs), norm)
+
+
+@pytest.mark.parametrize("cfg,n", [(1, 3000), (0, 65)])
+def test_eval_threshold_zero_is_the_exact_kernel_bitwise(env, cfg, n):
+    torch, pyro, _lib, sur, gms = env
+    m = mechs.load_config(cfg)
+    gm = gms[cfg]
+    model = _trained_like_surrogate(sur, m)
+    T, p, Y, rho = states(cfg, n, m.S, first=777)
+    r, t, y = to_dev(torch, rho, T, Y)
+    announce(f"surrogate eval thr=0 cfg{cfg} n={n}")
+    w, flags, count, _ = model.eval(gm, r, t, y, thr_spread=0.0, thr_resid=0.0)
+    exact = pyro.production_rates(gm, r, t, y)
+    torch.cuda.synchronize()
+    assert int(count.item()) == n and bool((flags == 1).all())
+    assert np.array_equal(w.cpu().numpy().view(np.uint64), exact.cpu().numpy().view(np.uint64))
+
+
+def _mlp_reference(torch, lib, model, m, gm, r, t, y, sur):
+    """Ensemble mean from the per-member forward kernel, transformed on the
+    host in FP64, and the indicators written out from their definitions."""
+    nrm = model.norm
+    fs, fc = to_dev(torch, nrm.feat_shift, nrm.feat_scale)
+    X = sur.features(gm, r, t, y, fs, fc)
+    n = X.shape[0]
+    Zs = []
+    for e in range(model.members):
+        Wd = torch.from_numpy(model.weights[e].view(np.int16).copy()).cuda()
+        bd = torch.from_numpy(model.biases[e].copy()).cuda()
+        acts = torch.empty(6 * n * model.hidden, dtype=torch.int16, device="cuda")
+        Z = torch.empty((n, 64), dtype=torch.float32, device="cuda")
+        assert lib.pyro_mlp_forward(model.hidden, n, _p(X), _p(Wd), _p(bd), _p(acts), _p(Z),
+                                    _s(torch)) == 0
+        Zs.append(Z.cpu().numpy()[:, :m.S].astype(np.float64))
+    Zs = np.stack(Zs)
+    zm = Zs.mean(axis=0)
+    w = (nrm.target_scale[:, None]
+         * np.sinh(nrm.target_mean[:, None] + nrm.target_std[:, None] * zm.T))
+    spread = np.sqrt(((Zs - zm) ** 2).sum(axis=(0, 2)) / model.members) / np.sqrt((zm ** 2).sum(1))
+    A = m.composition.astype(np.float64)
+    resid = np.sqrt(((A @ w) ** 2).sum(0)) / np.sqrt(((np.abs(A) @ np.abs(w)) ** 2).sum(0))
+    return w, spread, resid, Zs
+
+
+def test_eval_without_fallback_is_the_ensemble_mean(env):
+    torch, pyro, _lib, sur, gms = env
+    m = mechs.load_config(1)
+    gm = gms[1]
+    model = _trained_like_surrogate(sur, m)
+    n = 2000 + 17
+    T, p, Y, rho = states(4, n, m.S, first=4096)
+    r, t, y = to_dev(torch, rho, T, Y)
+    announce(f"surrogate eval thr=inf n={n}")
+    w, flags, count, ind = model.eval(gm, r, t, y, indicators=True)
+    torch.cuda.synchronize()
+    wr, spread, resid, Zs = _mlp_reference(torch, _lib.lib(), model, m, gm, r, t, y, sur)
+    assert int(count.item()) == 0 and bool((flags == 0).all())
+    got = w.cpu().numpy()
+    # the GPU averages the members in FP32 (two roundings of at most one
+    # FP32 step of max |z|) before the FP64 transform, whose derivative
+    # with respect to z is sigma sqrt(s^2 + omega^2)
+    dz = 2 * 2.0 ** -24 * np.abs(Zs).max(axis=0).T
+    tol = nrm_deriv(model, wr) * model.norm.target_std[:, None] * dz * 1.01 + 1e-300
+    assert np.all(np.abs(got - wr) <= tol)
+    ind = ind.cpu().numpy()
+    assert np.allclose(ind[0], spread, rtol=1e-5, atol=1e-12)
+    assert np.allclose(ind[1], resid, rtol=1e-5, atol=1e-12)
+
+
+def nrm_deriv(model, w):
+    """d omega / d(mu + sigma z) = s cosh(asinh(omega/s)) = sqrt(s^2 + omega^2)."""
+    s = model.norm.target_scale[:, None]
+    return np.sqrt(s * s + w * w)
+
+
+def test_eval_mixed_thresholds_route_cells_by_their_indicators(env):
+    torch, pyro, _lib, sur, gms = env
+    m = mechs.load_config(1)
+    gm = gms[1]
+    model = _trained_like_surrogate(sur, m)
+    n = 5000 + 3
+    T, p, Y, rho = states(4, n, m.S, first=9000)
+    r, t, y = to_dev(torch, rho, T, Y)
+    announce(f"surrogate eval mixed thresholds n={n}")
+    w_inf, _, _, ind = model.eval(gm, r, t, y, indicators=True)
+    w_inf = w_inf.cpu().numpy()
+    ind = ind.cpu().numpy()
+    ts, tr = float(np.median(ind[0])), float(np.quantile(ind[1], 0.7))
+    w, flags, count, _ = model.eval(gm, r, t, y, thr_spread=ts, thr_resid=tr)
+    exact = pyro.production_rates(gm, r, t, y).cpu().numpy()
+    torch.cuda.synchronize()
+    f = flags.cpu().numpy().astype(bool)
+    expect = ~((ind[0] < ts) & (ind[1] < tr) & np.isfinite(w_inf).all(axis=0))
+    assert np.array_equal(f, expect)
+    assert int(count.item()) == int(f.sum()) and 0 < f.sum() < n
+    got = w.cpu().numpy()
+    assert np.array_equal(got[:, f].view(np.uint64), exact[:, f].view(np.uint64))
+    assert np.array_equal(got[:, ~f].view(np.uint64), w_inf[:, ~f].view(np.uint64))
+
+
+def test_eval_rejects_bad_arguments(env):
+    torch, pyro, _lib, sur, gms = env
+    m = mechs.load_config(1)
+    model = _trained_like_surrogate(sur, m)
+    T, p, Y, rho = states(4, 100, m.S)
+    r, t, y = to_dev(torch, rho, T, Y)
+    ws, need = model.workspace(gms[1], 100)
+    st = model._device()
+    out = torch.empty_like(y)
+    flags = torch.empty(100, dtype=torch.uint8, device="cuda")
+    cnt = torch.empty(1, dtype=torch.int64, device="cuda")
+    lib = _lib.lib()
+    rc = lib.pyro_surrogate_eval(gms[1].handle, ctypes.byref(st), 100, 100, _p(r), _p(t), _p(y),
+                                 1.0, 1.0, _p(out), _p(flags), _p(cnt), None, _p(ws), need - 1,
+                                 _s(torch))
+    assert rc == _lib.PYRO_E_ARG and "workspace" in _lib.last_error()
+
+
+def test_training_reduces_the_loss(env):
+    """A few epochs on exact-kernel labels of 2^15 seeded states lower the
+    mean squared error of the normalised targets well below its start."""
+    torch, pyro, _lib, sur, gms = env
+    gm = gms[1]
+    announce("surrogate training 2^15 states")
+    data, norm = sur.build_dataset(gm, 1 << 15, seed=4000, sample=1 << 15, threads=4)
+    tr, hist = sur.train_member(data, 128, seed=sur.INIT_SEED, epochs=6, batch=1024, lr=2e-3,
+                                warmup=20)
+    announce(f"  mse by epoch {[f'{h:.3e}' for h in hist]}")
+    assert all(np.isfinite(hist))
+    assert hist[-1] < 0.5 * hist[0]
+    # normalised targets have unit variance: the network must beat the mean
+    assert hist[-1] < 0.5
