@@ -260,14 +260,26 @@ PYRO_API int pyro_surrogate_targets(const pyro_mech* mech, int64_t n, int64_t ld
                                     const double* mean, const double* std_dev, float* Zt,
                                     void* stream);
 
-/* Bytes of device workspace pyro_surrogate_eval needs for n cells. */
+/* Bytes of device workspace pyro_surrogate_eval and pyro_surrogate_outputs
+ * need for n cells (0 for an unsupported hidden width: evaluation supports
+ * H = 64, 128, 256). */
 PYRO_API size_t pyro_surrogate_workspace_size(const pyro_mech* mech, int64_t n, int hidden,
                                               int members);
+/* Raw outputs Z [members][n][64] (FP32, device) of every member on the cells,
+ * from the same fused kernel as pyro_surrogate_eval (before the ensemble mean
+ * and the inverse transform).  workspace: device, 256-byte aligned. */
+PYRO_API int pyro_surrogate_outputs(const pyro_mech* mech, const pyro_surrogate* sur,
+                                    int64_t n, int64_t ld, const double* rho, const double* T,
+                                    const double* Y, float* Z, void* workspace,
+                                    size_t workspace_bytes, void* stream);
 /*
- * Surrogate evaluation with fallback: wdot [S*ld] receives the ensemble-mean
- * prediction, then the exact production rates for every cell that is not
- * kept: a cell is kept only if its prediction is finite, its ensemble spread
- * is below thr_spread and its element residual below thr_resid (strictly).  fell_back[n] (device u8) marks those
+ * Surrogate evaluation with fallback: wdot [S*ld] receives the prediction
+ * omega_k = s_k sinh(mu_k + sigma_k zbar_k) from the ensemble-mean output
+ * zbar, then the exact production rates for every cell that is not kept: a
+ * cell is kept only if its prediction is finite, its ensemble spread
+ * sqrt(sum_e ||omega^e - omega||^2 / E) / ||omega|| (omega^e from member e
+ * alone) is below thr_spread and its element residual
+ * ||A omega|| / || |A| |omega| || is below thr_resid (both strictly).  fell_back[n] (device u8) marks those
  * cells, *n_fallback (device int64) counts them; indicators, if not NULL,
  * receives the spread [n] then the residual [n].  thr = 0 sends every cell
  * to the exact kernel, +inf none.

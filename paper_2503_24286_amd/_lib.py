@@ -80,6 +80,8 @@ SIGNATURES.update({
     "pyro_surrogate_workspace_size": (_SZ, [_P, _I64, _I, _I]),
     "pyro_surrogate_eval": (_I, [_P, ctypes.POINTER(Surrogate), _I64, _I64, _P, _P, _P, _D, _D,
                                  _P, _P, _P, _P, _P, _SZ, _P]),
+    "pyro_surrogate_outputs": (_I, [_P, ctypes.POINTER(Surrogate), _I64, _I64, _P, _P, _P, _P, _P,
+                                    _SZ, _P]),
 })
 
 _lib = None

@@ -78,6 +78,45 @@ hipError_t forward(const Layout& L, int64_t B, const uint16_t* X, const uint16_t
     return hipSuccess;
 }
 
+int check_surrogate(const pyro_mech* m, const pyro_surrogate* sur, int64_t n, int64_t ld) {
+    if (!m || !sur) return fail(PYRO_E_ARG, "null mechanism or surrogate");
+    if (n < 0 || ld < n) return fail(PYRO_E_ARG, "bad n or ld");
+    if (int rc = check_hidden(sur->hidden)) return rc;
+    if (!fused_supported(sur->hidden))
+        return fail(PYRO_E_UNSUPPORTED, "surrogate evaluation supports hidden widths 64, 128, 256");
+    if (sur->n_members < 1 || sur->n_members > kMaxMembers)
+        return fail(PYRO_E_ARG, "n_members must be in [1, 4]");
+    if (m->S + 3 > kFeatPad) return fail(PYRO_E_UNSUPPORTED, "surrogate supports at most 61 species");
+    if (!sur->weights || !sur->biases || !sur->feat_shift || !sur->feat_scale ||
+        !sur->target_scale || !sur->target_mean || !sur->target_std)
+        return fail(PYRO_E_ARG, "null pointer in the surrogate description");
+    return PYRO_OK;
+}
+
+struct Packed {
+    uint16_t* wp;
+    float* bp;
+    int64_t w_stride, b_stride;
+    unsigned char* rest;
+};
+
+// packs every member's weights into the fragment order of the fused kernel
+Packed pack(const pyro_surrogate* sur, void* workspace, hipStream_t s, hipError_t* e) {
+    const Layout L(sur->hidden);
+    Packed p;
+    p.w_stride = packed_weight_elems(sur->hidden);
+    p.b_stride = L.b_total;
+    unsigned char* q = static_cast<unsigned char*>(workspace);
+    p.wp = reinterpret_cast<uint16_t*>(q);
+    q += (size_t(sur->n_members) * p.w_stride * 2 + 255) / 256 * 256;
+    p.bp = reinterpret_cast<float*>(q);
+    q += (size_t(sur->n_members) * p.b_stride * 4 + 255) / 256 * 256;
+    p.rest = q;
+    *e = launch_pack(sur->hidden, sur->n_members, L.w_total, L.b_total, sur->weights,
+                     sur->biases, p.wp, p.bp, s);
+    return p;
+}
+
 }  // namespace
 }  // namespace pyro
 
@@ -243,19 +282,43 @@ int pyro_surrogate_targets(const pyro_mech* m, int64_t n, int64_t ld, const doub
 }
 
 size_t pyro_surrogate_workspace_size(const pyro_mech* m, int64_t n, int hidden, int members) {
-    if (!m || n < 0 || check_hidden(hidden) || members < 1 || members > kMaxMembers) return 0;
+    if (!m || n < 0 || check_hidden(hidden) || !fused_supported(hidden) || members < 1 ||
+        members > kMaxMembers)
+        return 0;
+    const Layout L(hidden);
     const int64_t nb = compaction_blocks(n);
     size_t b = 0;
     auto add = [&](size_t bytes) { b += (bytes + 255) / 256 * 256; };
-    add(size_t(n) * kFeatPad * 2);                  // features
-    add(size_t(n) * hidden * 2 * 2);                // activation ping-pong
-    add(size_t(members) * n * kOutPad * 4);          // member outputs
-    add(size_t(nb + 1) * 8);                         // block counts
-    add(8);                                          // fallback count
-    add(size_t(n) * 8);                              // indices
-    add(size_t(n) * 8 * 2);                          // compact rho, T
-    add(size_t(n) * m->S * 8 * 2);                   // compact Y, omega
+    add(size_t(members) * packed_weight_elems(hidden) * 2);  // packed weights
+    add(size_t(members) * L.b_total * 4);                    // packed biases
+    add(size_t(nb + 1) * 8);                                 // block counts
+    add(size_t(n) * 8);                                      // indices
+    add(size_t(n) * 8 * 2);                                  // compact rho, T
+    add(size_t(n) * m->S * 8 * 2);                           // compact Y, omega
     return b;
+}
+
+int pyro_surrogate_outputs(const pyro_mech* m, const pyro_surrogate* sur, int64_t n, int64_t ld,
+                           const double* rho, const double* T, const double* Y, float* Z,
+                           void* workspace, size_t workspace_bytes, void* stream) {
+    clear_error();
+    if (int rc = check_surrogate(m, sur, n, ld)) return rc;
+    if (n == 0) return PYRO_OK;
+    if (!rho || !T || !Y || !Z || !workspace) return fail(PYRO_E_ARG, "null pointer argument");
+    if (!aligned16(sur->weights) || (reinterpret_cast<uintptr_t>(workspace) & 255u))
+        return fail(PYRO_E_ARG, "weights must be 16-byte and the workspace 256-byte aligned");
+    const size_t need = pyro_surrogate_workspace_size(m, n, sur->hidden, sur->n_members);
+    if (workspace_bytes < need)
+        return fail(PYRO_E_ARG, "workspace too small: need " + std::to_string(need) + " bytes");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e;
+    const Packed p = pack(sur, workspace, s, &e);
+    if (e == hipSuccess)
+        e = launch_fused(m, sur->hidden, sur->n_members, n, ld, rho, T, Y, p.wp, p.bp, p.w_stride,
+                         p.b_stride, sur->feat_shift, sur->feat_scale, sur->target_scale,
+                         sur->target_mean, sur->target_std, 0.0, 0.0, nullptr, nullptr, nullptr, Z,
+                         s);
+    return e == hipSuccess ? PYRO_OK : hip_fail(e, "surrogate output launch");
 }
 
 int pyro_surrogate_eval(const pyro_mech* m, const pyro_surrogate* sur, int64_t n, int64_t ld,
@@ -264,16 +327,8 @@ int pyro_surrogate_eval(const pyro_mech* m, const pyro_surrogate* sur, int64_t n
                         int64_t* n_fallback, double* indicators, void* workspace,
                         size_t workspace_bytes, void* stream) {
     clear_error();
-    if (!m || !sur) return fail(PYRO_E_ARG, "null mechanism or surrogate");
-    if (n < 0 || ld < n) return fail(PYRO_E_ARG, "bad n or ld");
-    if (int rc = check_hidden(sur->hidden)) return rc;
-    if (sur->n_members < 1 || sur->n_members > kMaxMembers)
-        return fail(PYRO_E_ARG, "n_members must be in [1, 4]");
-    if (m->S + 3 > kFeatPad || m->E > kMaxElements)
-        return fail(PYRO_E_UNSUPPORTED, "surrogate supports at most 61 species and 16 elements");
-    if (!sur->weights || !sur->biases || !sur->feat_shift || !sur->feat_scale ||
-        !sur->target_scale || !sur->target_mean || !sur->target_std)
-        return fail(PYRO_E_ARG, "null pointer in the surrogate description");
+    if (int rc = check_surrogate(m, sur, n, ld)) return rc;
+    if (m->E > kMaxElements) return fail(PYRO_E_UNSUPPORTED, "surrogate supports at most 16 elements");
     if (n == 0) return PYRO_OK;
     if (!rho || !T || !Y || !wdot || !fell_back || !n_fallback || !workspace)
         return fail(PYRO_E_ARG, "null pointer argument");
@@ -283,53 +338,29 @@ int pyro_surrogate_eval(const pyro_mech* m, const pyro_surrogate* sur, int64_t n
     if (workspace_bytes < need)
         return fail(PYRO_E_ARG, "workspace too small: need " + std::to_string(need) + " bytes");
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const int H = sur->hidden;
-    const Layout L(H);
+    hipError_t e;
+    const Packed p = pack(sur, workspace, s, &e);
     const int64_t nb = compaction_blocks(n);
-    unsigned char* p = static_cast<unsigned char*>(workspace);
+    unsigned char* q = p.rest;
     auto take = [&](size_t bytes) {
-        unsigned char* q = p;
-        p += (bytes + 255) / 256 * 256;
-        return q;
+        unsigned char* r = q;
+        q += (bytes + 255) / 256 * 256;
+        return r;
     };
-    uint16_t* X = reinterpret_cast<uint16_t*>(take(size_t(n) * kFeatPad * 2));
-    uint16_t* act = reinterpret_cast<uint16_t*>(take(size_t(n) * H * 2 * 2));
-    float* Z = reinterpret_cast<float*>(take(size_t(sur->n_members) * n * kOutPad * 4));
     int64_t* counts = reinterpret_cast<int64_t*>(take(size_t(nb + 1) * 8));
-    (void)take(8);
     int64_t* idx = reinterpret_cast<int64_t*>(take(size_t(n) * 8));
     double* rc = reinterpret_cast<double*>(take(size_t(n) * 8 * 2));
     double* tc = rc + n;
     double* yc = reinterpret_cast<double*>(take(size_t(n) * m->S * 8 * 2));
     double* wc = yc + size_t(n) * m->S;
 
-    hipError_t e = launch_features(m, n, ld, rho, T, Y, sur->feat_shift, sur->feat_scale, X, s);
-    // each member: three SiLU layers through the ping-pong buffers, then the
-    // linear output layer (pre-activations are not kept)
-    for (int mem = 0; mem < sur->n_members && e == hipSuccess; ++mem) {
-        const uint16_t* W = sur->weights + size_t(mem) * L.w_total;
-        const float* b = sur->biases + size_t(mem) * L.b_total;
-        const uint16_t* in = X;
-        int64_t ldin = kFeatPad;
-        for (int l = 0; l < 4 && e == hipSuccess; ++l) {
-            GemmArgs g = nn(in, ldin, W + L.w[l], n, L.nout[l], L.kin[l]);
-            g.bias = b + L.b[l];
-            if (l < 3) {
-                uint16_t* out = act + size_t(l & 1) * n * H;
-                g.C_bf16 = out;
-                g.P_bf16 = nullptr;
-                e = launch_gemm(g, kEpiBiasSilu, 1, s);
-                in = out;
-                ldin = H;
-            } else {
-                g.C_f32 = Z + size_t(mem) * n * kOutPad;
-                e = launch_gemm(g, kEpiBiasF32, 1, s);
-            }
-        }
-    }
+    // prediction, indicators and flags in one pass; then the flagged cells,
+    // compacted in ascending order, through the exact kernel
     if (e == hipSuccess)
-        e = launch_post(m, n, ld, sur->n_members, Z, sur->target_scale, sur->target_mean,
-                        sur->target_std, thr_spread, thr_resid, wdot, fell_back, indicators, s);
+        e = launch_fused(m, sur->hidden, sur->n_members, n, ld, rho, T, Y, p.wp, p.bp, p.w_stride,
+                         p.b_stride, sur->feat_shift, sur->feat_scale, sur->target_scale,
+                         sur->target_mean, sur->target_std, thr_spread, thr_resid, wdot,
+                         fell_back, indicators, nullptr, s);
     if (e == hipSuccess) e = launch_compaction(n, fell_back, counts, n_fallback, idx, s);
     if (e == hipSuccess) e = launch_gather(m->S, n, ld, n_fallback, idx, rho, T, Y, rc, tc, yc, s);
     if (e == hipSuccess)

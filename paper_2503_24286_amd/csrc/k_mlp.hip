@@ -248,8 +248,9 @@ int64_t mse_partials(int64_t M, int ld) { return (M * ld + 255) / 256; }
 hipError_t launch_adamw(int64_t n, float* w, uint16_t* w_bf16, const float* grad, float* m1,
                         float* m2, float lr, float b1, float b2, float eps, float wd, int step,
                         hipStream_t stream) {
-    const float c1 = 1.0f - powf(b1, float(step));
-    const float c2 = 1.0f - powf(b2, float(step));
+    // bias corrections in FP64: 1 - b2^t cancels badly in FP32 for b2 near 1
+    const float c1 = float(1.0 - pow(double(b1), double(step)));
+    const float c2 = float(1.0 - pow(double(b2), double(step)));
     hipLaunchKernelGGL(adamw_kernel, dim3(unsigned((n + 255) / 256)), dim3(256), 0, stream, n, w,
                        w_bf16, grad, m1, m2, lr, b1, b2, eps, wd, c1, c2);
     return hipGetLastError();

@@ -1,0 +1,397 @@
+// Fused surrogate inference: features, every ensemble member's four layers,
+// the ensemble mean, the inverse target transform and the error indicators,
+// in one pass over the cells.  Activations never leave registers.
+//
+// One wavefront owns 32 cells.  Each layer is computed transposed,
+// out^T [N x 32 cells] = W^T [N x K] in^T [K x 32 cells], with
+// v_mfma_f32_32x32x16_bf16: the A operand (weights) is a pre-packed 16-byte
+// fragment per lane read from global memory (L1/L2-resident: every wave
+// reads the same 160 K weights), the B operand is the previous layer's
+// output.  Lane l holds, for cell l%32, the outputs 8(i/4) + 4(l/32) + i%4
+// of each 32-row block (register i).  Reading registers 8t..8t+7 of block
+// ob as the B operand of K-step 2 ob + t therefore sums over the inputs
+// 32 ob + 16 t + 8(j/4) + 4(l/32) + j%4 (j = 0..7) of the next layer; the
+// packed weights of layers 2..4 follow that order, so no data moves
+// between layers.
+//
+// Weight fragments: [ob][ks][lane][8] per layer, ob = output block of 32,
+// ks = K-step of 16; biases [ob][l/32][16] in the register order above.
+#include "pyro_internal.h"
+#include "surrogate_internal.h"
+
+namespace pyro {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kCells = 32;                 // cells per wavefront
+constexpr int kWavesPerBlock = 4;
+constexpr int kFeatRow = kFeatPad + 8;     // padded LDS feature row (bf16)
+constexpr int kFeatBytes = kWavesPerBlock * kCells * kFeatRow * 2;
+
+__host__ __device__ constexpr size_t fused_lds_bytes(int members) {
+    return size_t(kFeatBytes) + size_t(kWavesPerBlock) * members * 32 * 64 * 4;
+}
+
+__device__ inline uint16_t f2bf(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u) return uint16_t((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return uint16_t(u >> 16);
+}
+
+__device__ inline float silu(float x) { return x / (1.0f + __expf(-x)); }
+
+// packed-fragment sizes (elements) of one member for hidden width H
+__host__ __device__ constexpr int64_t frag_elems(int nb, int ks) { return int64_t(nb) * ks * 64 * 8; }
+
+struct PackLayout {
+    int64_t w_off[4], b_off[4];
+    int nb[4], ks[4];
+    __host__ __device__ explicit PackLayout(int H) {
+        const int K[4] = {kFeatPad, H, H, H}, N[4] = {H, H, H, kOutPad};
+        int64_t ow = 0, ob = 0;
+        for (int l = 0; l < 4; ++l) {
+            nb[l] = N[l] / 32;
+            ks[l] = K[l] / 16;
+            w_off[l] = ow;
+            b_off[l] = ob;
+            ow += frag_elems(nb[l], ks[l]);
+            ob += N[l];
+        }
+    }
+};
+
+// input index of K-slot (8 h + j) of K-step ks: natural for the feature
+// layer, the register order of the previous layer's outputs otherwise
+__host__ __device__ inline int input_index(int layer, int ks, int h, int j) {
+    if (layer == 0) return 16 * ks + 8 * h + j;
+    return 32 * (ks >> 1) + 16 * (ks & 1) + 8 * (j >> 2) + 4 * h + (j & 3);
+}
+
+// output index of register i in block ob for lane half h
+__host__ __device__ inline int output_index(int ob, int h, int i) {
+    return 32 * ob + 8 * (i >> 2) + 4 * h + (i & 3);
+}
+
+__global__ void pack_kernel(int H, int members, int64_t w_total, int64_t b_total,
+                            const uint16_t* __restrict__ W, const float* __restrict__ b,
+                            uint16_t* __restrict__ wp, float* __restrict__ bp) {
+    const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const PackLayout P(H);
+    const int K[4] = {kFeatPad, H, H, H}, N[4] = {H, H, H, kOutPad};
+    if (t < w_total * members) {
+        const int e = int(t / w_total);
+        const int64_t p = t % w_total;
+        int l = 3;
+        while (l > 0 && p < P.w_off[l]) --l;
+        const int64_t q = p - P.w_off[l];
+        const int j = int(q & 7), lane = int((q >> 3) & 63);
+        const int64_t frag = q >> 9;
+        const int ks = int(frag % P.ks[l]), ob = int(frag / P.ks[l]);
+        // natural weights of layer l: [K][N] row-major after the previous layers
+        int64_t nat = 0;
+        for (int i = 0; i < l; ++i) nat += int64_t(K[i]) * N[i];
+        const int in = input_index(l, ks, lane >> 5, j), out = 32 * ob + (lane & 31);
+        wp[t] = W[e * w_total + nat + int64_t(in) * N[l] + out];
+    }
+    if (t < b_total * members) {
+        const int e = int(t / b_total);
+        const int64_t p = t % b_total;
+        int l = 3;
+        while (l > 0 && p < P.b_off[l]) --l;
+        const int q = int(p - P.b_off[l]);
+        const int ob = q >> 5, h = (q >> 4) & 1, i = q & 15;
+        bp[t] = b[e * b_total + P.b_off[l] + output_index(ob, h, i)];
+    }
+}
+
+struct FusedArgs {
+    const uint16_t* wp;    // packed weights, members after one another
+    const float* bp;       // packed biases
+    int64_t w_stride, b_stride;
+    const float* shift;
+    const float* scale;
+    const double* ts;
+    const double* tmu;
+    const double* tsig;
+    double thr_spread, thr_resid;
+    double* wdot;          // eval: [S][ld]
+    uint8_t* flag;         // eval: [n]
+    double* ind;           // eval, optional: spread [n], residual [n]
+    float* zout;           // raw mode: [members][n][64]
+};
+
+template <int NB, int KS>
+__device__ inline void layer(f32x16 (&acc)[NB], const bf16x8 (&in)[KS], const uint16_t* __restrict__ wp,
+                             const float* __restrict__ bp, int lane) {
+    const int h = lane >> 5;
+#pragma unroll
+    for (int ob = 0; ob < NB; ++ob) {
+        const float4* bq = reinterpret_cast<const float4*>(bp + ob * 32 + h * 16);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const float4 v = bq[q];
+            acc[ob][4 * q] = v.x;
+            acc[ob][4 * q + 1] = v.y;
+            acc[ob][4 * q + 2] = v.z;
+            acc[ob][4 * q + 3] = v.w;
+        }
+    }
+    const u32x4* frag = reinterpret_cast<const u32x4*>(wp) + lane;
+    // fragments of K-step ks + 1 are in flight while step ks multiplies
+    u32x4 cur[NB], nxt[NB];
+#pragma unroll
+    for (int ob = 0; ob < NB; ++ob) cur[ob] = frag[(ob * KS) * 64];
+    // fully unrolled: the operand array is indexed by compile-time constants
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+        if (ks + 1 < KS) {
+#pragma unroll
+            for (int ob = 0; ob < NB; ++ob) nxt[ob] = frag[(ob * KS + ks + 1) * 64];
+        }
+#pragma unroll
+        for (int ob = 0; ob < NB; ++ob)
+            acc[ob] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                __builtin_bit_cast(bf16x8, cur[ob]), in[ks], acc[ob], 0, 0, 0);
+#pragma unroll
+        for (int ob = 0; ob < NB; ++ob) cur[ob] = nxt[ob];
+    }
+}
+
+// bias-added outputs -> SiLU -> BF16 inputs of the next layer
+template <int NB>
+__device__ inline void activate(const f32x16 (&acc)[NB], bf16x8 (&out)[2 * NB]) {
+#pragma unroll
+    for (int ob = 0; ob < NB; ++ob)
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            u32x4 packed;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const uint32_t lo = f2bf(silu(acc[ob][8 * t + 2 * q]));
+                const uint32_t hi = f2bf(silu(acc[ob][8 * t + 2 * q + 1]));
+                packed[q] = lo | (hi << 16);
+            }
+            out[2 * ob + t] = __builtin_bit_cast(bf16x8, packed);
+        }
+}
+
+template <int H, int E, bool RAW>
+__global__ __launch_bounds__(kWavesPerBlock * 64) void fused_kernel(
+    DevMech m, int64_t n, int64_t ld, const double* __restrict__ rho,
+    const double* __restrict__ T, const double* __restrict__ Y, FusedArgs a) {
+    constexpr int NBH = H / 32, KSH = H / 16;
+    // LDS: feature rows [wave][cell][kFeatRow] (BF16), then the member
+    // outputs [wave][member][register][lane] (FP32, lane-contiguous)
+    extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    uint16_t* feat = reinterpret_cast<uint16_t*>(lds) + wv * kCells * kFeatRow;
+    float* zl = reinterpret_cast<float*>(lds + kFeatBytes) + wv * E * 32 * 64 + lane;
+    const int64_t c0 = (int64_t(blockIdx.x) * kWavesPerBlock + wv) * kCells;
+    if (c0 >= n) return;  // whole wavefront; the kernel has no block barrier
+    const int cl = lane & 31, h = lane >> 5;
+    const int64_t cell = c0 + cl;
+    const bool valid = cell < n;
+    const int64_t c = valid ? cell : n - 1;
+
+    // ---- features of the 32 cells, staged in this wave's LDS rows; lane
+    // half h converts the species k = h, h + 2, ...
+    uint16_t* fr = feat + cl * kFeatRow;
+    const double Tc = T[c];
+    double x = 0.0;  // partial 1/W
+    for (int k = h; k < m.S; k += 2) {
+        const double y = Y[size_t(k) * ld + c];
+        x = fma(y, m.newton[k].inv_w, x);
+        fr[k + 2] = f2bf(float((log(fmax(y, 0.0) + 1e-12) - a.shift[k + 2]) * a.scale[k + 2]));
+    }
+    x += __shfl_xor(x, 32);
+    if (h == 0) {
+        const double p = rho[c] * kGasConstant * Tc * x;
+        fr[0] = f2bf(float((Tc * 1e-3 - a.shift[0]) * a.scale[0]));
+        fr[1] = f2bf(float((log10(p) - a.shift[1]) * a.scale[1]));
+    } else {
+        for (int f = m.S + 2; f < kFeatPad; ++f) fr[f] = f == m.S + 2 ? uint16_t(0x3f80) : uint16_t(0);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    bf16x8 xb[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) xb[s] = *reinterpret_cast<const bf16x8*>(fr + 16 * s + 8 * h);
+
+    // ---- ensemble members (the loop stays rolled: one member's code is
+    // already 320 MFMAs, and its outputs go to LDS)
+#pragma nounroll
+    for (int e = 0; e < E; ++e) {
+        const PackLayout P(H);
+        const uint16_t* wp = a.wp + e * a.w_stride;
+        const float* bp = a.bp + e * a.b_stride;
+        f32x16 acc[NBH];
+        bf16x8 act[KSH];
+        layer<NBH, 4>(acc, xb, wp + P.w_off[0], bp + P.b_off[0], lane);
+        activate<NBH>(acc, act);
+        layer<NBH, KSH>(acc, act, wp + P.w_off[1], bp + P.b_off[1], lane);
+        activate<NBH>(acc, act);
+        layer<NBH, KSH>(acc, act, wp + P.w_off[2], bp + P.b_off[2], lane);
+        activate<NBH>(acc, act);
+        f32x16 z[2];
+        layer<2, KSH>(z, act, wp + P.w_off[3], bp + P.b_off[3], lane);
+#pragma unroll
+        for (int ob = 0; ob < 2; ++ob)
+#pragma unroll
+            for (int i = 0; i < 16; ++i) zl[(e * 32 + ob * 16 + i) * 64] = z[ob][i];
+    }
+    // outputs are read back by the lane that wrote them: no wave exchange
+
+    if constexpr (RAW) {
+        if (valid) {
+            for (int e = 0; e < E; ++e)
+#pragma unroll
+                for (int ob = 0; ob < 2; ++ob)
+#pragma unroll
+                    for (int i = 0; i < 16; ++i)
+                        a.zout[(int64_t(e) * n + cell) * kOutPad + output_index(ob, h, i)] =
+                            zl[(e * 32 + ob * 16 + i) * 64];
+        }
+        return;
+    } else {
+        // ---- ensemble mean, inverse transform, indicators (this lane's 32
+        // outputs; per-cell sums completed with the other lane half)
+        const float inv_e = 1.0f / float(E);
+        double wm[2][16];
+        double mean2 = 0.0, dev2 = 0.0;
+        bool finite = true;
+#pragma unroll
+        for (int ob = 0; ob < 2; ++ob)
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const int k = output_index(ob, h, i);
+                const int r = ob * 16 + i;
+                wm[ob][i] = 0.0;
+                if (k < m.S) {
+                    float zs = 0.0f;
+#pragma unroll
+                    for (int e = 0; e < E; ++e) zs += zl[(e * 32 + r) * 64];
+                    const double s = a.ts[k], mu = a.tmu[k], sg = a.tsig[k];
+                    const double w = s * sinh(fma(sg, double(zs * inv_e), mu));
+                    wm[ob][i] = w;
+                    finite = finite && isfinite(w);
+                    mean2 = fma(w, w, mean2);
+                    if (E > 1) {
+#pragma unroll
+                        for (int e = 0; e < E; ++e) {
+                            const double d =
+                                s * sinh(fma(sg, double(zl[(e * 32 + r) * 64]), mu)) - w;
+                            dev2 = fma(d, d, dev2);
+                        }
+                    }
+                    if (valid) a.wdot[size_t(k) * ld + cell] = w;
+                }
+            }
+        // element residual ||A w|| / || |A| |w| ||
+        double r2 = 0.0, q2 = 0.0;
+        for (int el = 0; el < m.E; ++el) {
+            const double* ce = m.comp + size_t(el) * m.S;
+            double r = 0.0, q = 0.0;
+#pragma unroll
+            for (int ob = 0; ob < 2; ++ob)
+#pragma unroll
+                for (int i = 0; i < 16; ++i) {
+                    const int k = output_index(ob, h, i);
+                    if (k < m.S) {
+                        const double ak = ce[k];
+                        r = fma(ak, wm[ob][i], r);
+                        q = fma(fabs(ak), fabs(wm[ob][i]), q);
+                    }
+                }
+            r += __shfl_xor(r, 32);
+            q += __shfl_xor(q, 32);
+            r2 = fma(r, r, r2);
+            q2 = fma(q, q, q2);
+        }
+        mean2 += __shfl_xor(mean2, 32);
+        dev2 += __shfl_xor(dev2, 32);
+        const int fin = __shfl_xor(int(finite), 32) & int(finite);
+        if (h == 0 && valid) {
+            const double spread = sqrt(dev2 / E) / fmax(sqrt(mean2), 1e-300);
+            const double resid = q2 > 0.0 ? sqrt(r2 / q2) : 0.0;
+            a.flag[cell] = (fin && spread < a.thr_spread && resid < a.thr_resid) ? 0 : 1;
+            if (a.ind) {
+                a.ind[cell] = spread;
+                a.ind[n + cell] = resid;
+            }
+        }
+    }
+}
+
+template <int H, int E>
+hipError_t launch_fused_he(const pyro_mech* m, int64_t n, int64_t ld, const double* rho,
+                           const double* T, const double* Y, const FusedArgs& a, bool raw,
+                           hipStream_t stream) {
+    const int64_t waves = (n + kCells - 1) / kCells;
+    const dim3 grid(unsigned((waves + kWavesPerBlock - 1) / kWavesPerBlock));
+    const size_t lds = fused_lds_bytes(E);
+    const void* fn = raw ? reinterpret_cast<const void*>(&fused_kernel<H, E, true>)
+                         : reinterpret_cast<const void*>(&fused_kernel<H, E, false>);
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+    if (e != hipSuccess) return e;
+    if (raw)
+        hipLaunchKernelGGL((fused_kernel<H, E, true>), grid, dim3(kWavesPerBlock * 64), lds,
+                           stream, m->dev, n, ld, rho, T, Y, a);
+    else
+        hipLaunchKernelGGL((fused_kernel<H, E, false>), grid, dim3(kWavesPerBlock * 64), lds,
+                           stream, m->dev, n, ld, rho, T, Y, a);
+    return hipGetLastError();
+}
+
+template <int H>
+hipError_t launch_fused_h(const pyro_mech* m, int members, int64_t n, int64_t ld,
+                          const double* rho, const double* T, const double* Y, const FusedArgs& a,
+                          bool raw, hipStream_t stream) {
+    switch (members) {
+        case 1: return launch_fused_he<H, 1>(m, n, ld, rho, T, Y, a, raw, stream);
+        case 2: return launch_fused_he<H, 2>(m, n, ld, rho, T, Y, a, raw, stream);
+        case 3: return launch_fused_he<H, 3>(m, n, ld, rho, T, Y, a, raw, stream);
+        default: return launch_fused_he<H, 4>(m, n, ld, rho, T, Y, a, raw, stream);
+    }
+}
+
+}  // namespace
+
+bool fused_supported(int hidden) { return hidden == 64 || hidden == 128 || hidden == 256; }
+
+int64_t packed_weight_elems(int hidden) {
+    const PackLayout P(hidden);
+    return P.w_off[3] + frag_elems(P.nb[3], P.ks[3]);
+}
+
+hipError_t launch_pack(int hidden, int members, int64_t w_total, int64_t b_total,
+                       const uint16_t* W, const float* b, uint16_t* wp, float* bp,
+                       hipStream_t stream) {
+    const int64_t count = (w_total > b_total ? w_total : b_total) * members;
+    hipLaunchKernelGGL(pack_kernel, dim3(unsigned((count + 255) / 256)), dim3(256), 0, stream,
+                       hidden, members, w_total, b_total, W, b, wp, bp);
+    return hipGetLastError();
+}
+
+hipError_t launch_fused(const pyro_mech* m, int hidden, int members, int64_t n, int64_t ld,
+                        const double* rho, const double* T, const double* Y,
+                        const uint16_t* wp, const float* bp, int64_t w_stride, int64_t b_stride,
+                        const float* shift, const float* scale, const double* ts,
+                        const double* tmu, const double* tsig, double thr_spread,
+                        double thr_resid, double* wdot, uint8_t* flag, double* ind, float* zout,
+                        hipStream_t stream) {
+    FusedArgs a{wp, bp, w_stride, b_stride, shift, scale, ts, tmu, tsig, thr_spread,
+                thr_resid, wdot, flag, ind, zout};
+    const bool raw = zout != nullptr;
+    switch (hidden) {
+        case 64: return launch_fused_h<64>(m, members, n, ld, rho, T, Y, a, raw, stream);
+        case 128: return launch_fused_h<128>(m, members, n, ld, rho, T, Y, a, raw, stream);
+        default: return launch_fused_h<256>(m, members, n, ld, rho, T, Y, a, raw, stream);
+    }
+}
+
+}  // namespace pyro

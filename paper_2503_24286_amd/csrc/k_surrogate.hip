@@ -1,16 +1,13 @@
-// The learned surrogate's per-cell pipeline: features, training targets,
-// ensemble post-processing with error indicators, and the deterministic
-// compaction, gather and scatter around the exact-kernel fallback.
+// The learned surrogate's per-cell helpers: training features and targets,
+// and the deterministic compaction, gather and scatter around the
+// exact-kernel fallback.
 //
-// Features (55 used of 64, BF16, one row per cell): T/1000, log10 p (p from
-// the equation of state, eq. eos), ln(max(Y_k, 0) + 1e-12), each shifted and
-// scaled by the training-set statistics, a constant 1, and zero padding.
+// Features (S + 3 used of 64, BF16, one row per cell): T/1000, log10 p (p
+// from the equation of state, eq. eos), ln(max(Y_k, 0) + 1e-12), each shifted
+// and scaled by the training-set statistics, a constant 1, and zero padding.
 // Targets: z_k = (asinh(omega_k / s_k) - mu_k) / sigma_k with s_k the median
 // |omega_k| of the training set, inverted as omega_k = s_k sinh(mu_k +
-// sigma_k z_k).  Indicators per cell: the ensemble spread
-// ||z^e - mean z|| / ||mean z|| and the element residual
-// ||A omega|| / || |A| |omega| || (atoms are conserved by every reaction, so
-// the exact omega has a zero residual).
+// sigma_k z_k).
 #include "pyro_internal.h"
 #include "surrogate_internal.h"
 
@@ -66,56 +63,6 @@ __global__ __launch_bounds__(kBlock) void targets_kernel(int S, int64_t n, int64
     for (int k = 0; k < kOutPad; ++k)
         Zt[i * kOutPad + k] =
             k < S ? float((asinh(wdot[size_t(k) * ld + i] / ts[k]) - tmu[k]) / tsig[k]) : 0.0f;
-}
-
-// Ensemble mean, inverse transform, indicators and the fallback flag.
-__global__ __launch_bounds__(kBlock) void post_kernel(DevMech m, int64_t n, int64_t ld,
-                                                      int members, const float* __restrict__ Z,
-                                                      const double* __restrict__ ts,
-                                                      const double* __restrict__ tmu,
-                                                      const double* __restrict__ tsig,
-                                                      double thr_spread, double thr_resid,
-                                                      double* __restrict__ wdot,
-                                                      uint8_t* __restrict__ flag,
-                                                      double* __restrict__ ind) {
-    const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
-    if (i >= n) return;
-    const float inv_e = 1.0f / float(members);
-    double dev2 = 0.0, mean2 = 0.0;
-    double res[kMaxElements], absres[kMaxElements];
-    for (int e = 0; e < m.E; ++e) res[e] = absres[e] = 0.0;
-    bool finite = true;
-    for (int k = 0; k < m.S; ++k) {
-        float zs = 0.0f;
-        for (int e = 0; e < members; ++e) zs += Z[(size_t(e) * n + i) * kOutPad + k];
-        const float zm = zs * inv_e;
-        for (int e = 0; e < members; ++e) {
-            const float d = Z[(size_t(e) * n + i) * kOutPad + k] - zm;
-            dev2 += double(d) * d;
-        }
-        mean2 += double(zm) * zm;
-        const double w = ts[k] * sinh(tmu[k] + tsig[k] * double(zm));
-        finite = finite && isfinite(w);
-        wdot[size_t(k) * ld + i] = w;
-        for (int e = 0; e < m.E; ++e) {
-            const double a = m.comp[e * m.S + k];
-            res[e] += a * w;
-            absres[e] += fabs(a) * fabs(w);
-        }
-    }
-    double r2 = 0.0, a2 = 0.0;
-    for (int e = 0; e < m.E; ++e) {
-        r2 += res[e] * res[e];
-        a2 += absres[e] * absres[e];
-    }
-    const double spread = sqrt(dev2 * inv_e) / fmax(sqrt(mean2), 1e-30);
-    const double resid = a2 > 0.0 ? sqrt(r2 / a2) : 0.0;
-    // kept only with both indicators strictly below their thresholds (NaN fails)
-    flag[i] = (finite && spread < thr_spread && resid < thr_resid) ? 0 : 1;
-    if (ind) {
-        ind[i] = spread;
-        ind[n + i] = resid;
-    }
 }
 
 // Compaction of the flagged cells in ascending order: per-block counts, one
@@ -224,15 +171,6 @@ hipError_t launch_targets(const pyro_mech* m, int64_t n, int64_t ld, const doubl
                           hipStream_t stream) {
     hipLaunchKernelGGL(targets_kernel, dim3(grid(n, kBlock)), dim3(kBlock), 0, stream, m->S, n, ld,
                        wdot, ts, tmu, tsig, Zt);
-    return hipGetLastError();
-}
-
-hipError_t launch_post(const pyro_mech* m, int64_t n, int64_t ld, int members, const float* Z,
-                       const double* ts, const double* tmu, const double* tsig, double thr_spread,
-                       double thr_resid, double* wdot, uint8_t* flag, double* ind,
-                       hipStream_t stream) {
-    hipLaunchKernelGGL(post_kernel, dim3(grid(n, kBlock)), dim3(kBlock), 0, stream, m->dev, n, ld,
-                       members, Z, ts, tmu, tsig, thr_spread, thr_resid, wdot, flag, ind);
     return hipGetLastError();
 }
 

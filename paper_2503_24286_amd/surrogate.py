@@ -8,10 +8,11 @@ training step is the library's forward GEMMs, MSE, backward GEMMs and AdamW.
 The host only draws the seeded states, computes normalisation statistics on a
 sample, schedules the steps and picks the fallback thresholds.
 
-Evaluation (``Surrogate.eval``) is one ``pyro_surrogate_eval`` call: the
-ensemble mean, the two error indicators (ensemble spread and element
-residual), and the exact kernel on every cell whose indicators are not below
-the thresholds.
+Evaluation (``Surrogate.eval``) is one ``pyro_surrogate_eval`` call: a fused
+kernel computes the features, every member's network, the ensemble mean, the
+inverse transform and the two error indicators (ensemble spread of omega and
+element residual), then the exact kernel runs on every cell whose indicators
+are not below the thresholds.
 """
 
 import ctypes
@@ -363,6 +364,19 @@ class Surrogate:
         if self._ws is None or self._ws.numel() < need:
             self._ws = torch.empty(max(need, 1), dtype=torch.uint8, device="cuda")
         return self._ws, need
+
+    def outputs(self, mech, rho, T, Y):
+        """Raw member outputs Z (members, n, 64) of the fused kernel."""
+        S, n = Y.shape
+        ld = api._species_major(Y, S, torch.float64, "Y")
+        api._cells(rho, n, torch.float64, "rho")
+        api._cells(T, n, torch.float64, "T")
+        Z = torch.empty((self.members, n, OUT_PAD), dtype=torch.float32, device=Y.device)
+        ws, need = self.workspace(mech, n)
+        st = self._device()
+        check(lib().pyro_surrogate_outputs(mech.handle, ctypes.byref(st), n, ld, _p(rho), _p(T),
+                                           _p(Y), _p(Z), _p(ws), need, _stream()))
+        return Z
 
     def eval(self, mech, rho, T, Y, thr_spread=None, thr_resid=None, out=None,
              indicators=False):
