@@ -132,9 +132,7 @@ int pyro_production_rates_vjp(const pyro_mech* m, int64_t n, int64_t ld, const d
     if (!params_bar) return fail(PYRO_E_ARG, "null pointer: params_bar");
     if (vjp_lds_bytes(m) > 160 * 1024)
         return fail(PYRO_E_UNSUPPORTED, "mechanism too large for the VJP tile");
-    if (m->dev.n_chunks > kWaves * 4)
-        return fail(PYRO_E_UNSUPPORTED, "too many reactions for the VJP kernel (at most 512)");
-    if (m->max_own > 16) return fail(PYRO_E_UNSUPPORTED, "too many species for the VJP kernel");
+    if (m->vjp_max_own > 16) return fail(PYRO_E_UNSUPPORTED, "too many species for the VJP kernel");
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (n == 0) {
         // no cells: every parameter gradient is zero

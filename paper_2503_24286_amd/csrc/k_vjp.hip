@@ -14,12 +14,15 @@
 //   Gbar_k G_k = sum_j (nu'_kj - nu''_kj) b_j,
 // so the species sums reuse the forward kernel's chunk/gather structure with
 // two LDS values per reaction.  Falloff reactions split xbar between the
-// high- and low-pressure triples through s = d ln k / d ln P_r.  The sums
-// over cells of xbar (1, ln T, -1/(R T)) are a contraction over the cells of
-// each tile, done with FP64 MFMA (v_mfma_f64_16x16x4f64) by one wave per
-// chunk and accumulated in registers across the tiles of a persistent
-// workgroup; a second kernel adds the per-workgroup partials in a fixed
-// order, so results are bitwise reproducible.
+// high- and low-pressure triples through s = d ln k / d ln P_r.
+//
+// A workgroup of 16 wavefronts works on one 64-cell tile at a time (one
+// reaction per wavefront per chunk of 16, from a schedule of its own), with
+// double-buffered chunk planes and one barrier per chunk.  The sums over the
+// tile's cells of xbar (1, ln T, -1/(R T)) are wavefront butterflies; the
+// owning wavefront adds them to the workgroup's accumulator in LDS, and a
+// second kernel adds the per-workgroup accumulators in a fixed order, so the
+// results are bitwise reproducible.
 #include <algorithm>
 
 #include "pyro_internal.h"
@@ -29,11 +32,8 @@ namespace {
 
 constexpr int kVRow = kTile * 24;                   // C[64], G[64], wbar[64]
 constexpr int kPlane = kChunk * kTile * 8;          // a or b: [slot][cell]
-constexpr int kXStride = kChunk + 1;                // padded row of a transposed plane
-constexpr int kXPlane = kTile * kXStride * 8;       // xbar: [cell][slot]
-constexpr int kChunkBytes = 2 * kPlane + 2 * kXPlane;
-constexpr int kMaxRound = 4;                        // chunks one wave reduces per tile
-typedef double d4 __attribute__((ext_vector_type(4)));
+constexpr int kBuf = 2 * kPlane;                    // one chunk buffer: a and b planes
+static_assert(kVjpWaves == kChunk, "one reaction per wavefront fills a chunk's slots");
 
 struct CGW {
     double c, g, w;
@@ -70,16 +70,12 @@ __device__ inline double pop_front(double (&v)[N]) {
     return head;
 }
 
-template <int N>
-__device__ inline void rotate(d4 (&v)[N]) {
-    const d4 head = v[0];
-#pragma unroll
-    for (int i = 0; i + 1 < N; ++i) v[i] = v[i + 1];
-    v[N - 1] = head;
-}
-
+// per-cell temperature terms; 1/(R T), R T/p0 and p0/(R T) are derived on use
 struct CellState {
-    double T, lnT, invT, invRT, rtp, irtp;
+    double T, lnT, invT;
+    __device__ double invRT() const { return invT * (1.0 / kGasConstant); }
+    __device__ double rtp() const { return T * (kGasConstant / kOneAtm); }
+    __device__ double irtp() const { return invT * (kOneAtm / kGasConstant); }
 };
 
 struct RevOut {
@@ -92,14 +88,14 @@ __device__ inline RevOut reaction_vjp(const DevMech& m, const RxnRec& r,
                                       const unsigned char* lds, int lane, double M,
                                       const CellState& cs) {
     const double* pr = params + 3 * r.prow;
-    const double kinf = exp(fma(-pr[2], cs.invRT, fma(pr[1], cs.lnT, pr[0])));
-    const double dxdT = fma(pr[2] * cs.invRT, cs.invT, pr[1] * cs.invT);
+    const double kinf = exp(fma(-pr[2], cs.invRT(), fma(pr[1], cs.lnT, pr[0])));
+    const double dxdT = fma(pr[2] * cs.invRT(), cs.invT, pr[1] * cs.invT);
     double keff = kinf, s = 0.0, dlnF_dT = 0.0, k0 = 0.0, F = 1.0, Pr = 0.0;
     double dlnF_dlnPr = 0.0, dx0dT = 0.0;
     if (r.cls >= kLindemann) {
         const double* pl = params + 3 * (m.R + r.fo);
-        k0 = exp(fma(-pl[2], cs.invRT, fma(pl[1], cs.lnT, pl[0])));
-        dx0dT = fma(pl[2] * cs.invRT, cs.invT, pl[1] * cs.invT);
+        k0 = exp(fma(-pl[2], cs.invRT(), fma(pl[1], cs.lnT, pl[0])));
+        dx0dT = fma(pl[2] * cs.invRT(), cs.invT, pl[1] * cs.invT);
         Pr = k0 * M / kinf;
         if (r.cls == kTroe) {
             const FalloffRec f = m.falloff[r.fo];
@@ -162,9 +158,9 @@ __device__ inline RevOut reaction_vjp(const DevMech& m, const RxnRec& r,
     if (r.rev) {
         double pw = 1.0;
         if (r.dnu > 0)
-            for (int i = 0; i < r.dnu; ++i) pw *= cs.rtp;
+            for (int i = 0; i < r.dnu; ++i) pw *= cs.rtp();
         else
-            for (int i = 0; i < -r.dnu; ++i) pw *= cs.irtp;
+            for (int i = 0; i < -r.dnu; ++i) pw *= cs.irtp();
         rev = pw * cgp * recip(gr);
     }
     const double Rf = keff * cr;
@@ -193,32 +189,33 @@ __device__ inline RevOut reaction_vjp(const DevMech& m, const RxnRec& r,
     return o;
 }
 
+// sum over the 64 lanes, bitwise identical in every lane and run
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
 template <int MAXOWN, int MAXPD>
-__global__ __launch_bounds__(kWaves * 64) void vjp_kernel(
+__global__ __launch_bounds__(kVjpWaves * 64) void vjp_kernel(
     DevMech m, int64_t n, int64_t ld, const double* __restrict__ rho,
     const double* __restrict__ T, const double* __restrict__ Y,
     const double* __restrict__ wbar, double* __restrict__ Ybar, double* __restrict__ Tbar,
     double* __restrict__ partial, const double* __restrict__ params) {
+    // LDS: species rows, two chunk buffers, Mbar [n_pd][64], parameter sums
     extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
+    const DevSched& sc = m.vjp;
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    unsigned char* chunk = lds + size_t(m.S) * kVRow;
-    unsigned char* plane_a = chunk;
-    unsigned char* plane_b = chunk + kPlane;
-    double* xT = reinterpret_cast<double*>(chunk + 2 * kPlane);
-    double* x0T = reinterpret_cast<double*>(chunk + 2 * kPlane + kXPlane);
-    double* mbar = reinterpret_cast<double*>(chunk + kChunkBytes);          // [n_pd][64]
-    double* fl = mbar + size_t(m.n_pd) * kTile;                                // lnT[64], -1/RT[64]
-    double* tb = reinterpret_cast<double*>(chunk);                            // [kWaves][64], aliases planes
+    unsigned char* bufs = lds + size_t(m.S) * kVRow;
+    double* mbar = reinterpret_cast<double*>(bufs + 2 * kBuf);                 // [n_pd][64]
+    double* pacc = mbar + size_t(m.n_pd) * kTile;                             // [R + n_fo][3]
+    const int n_rows = m.R + m.n_fo;
+    for (int i = threadIdx.x; i < 3 * n_rows; i += kVjpWaves * 64) pacc[i] = 0.0;
 
-    const int nown = m.n_own[w];
-    const int32_t* own = m.own + w * kMaxOwn;
-    const int npdw = m.n_pdw[w];
-    // chunks this wave reduces per tile: w, w + kWaves, ...
-    const int my_rounds = m.n_chunks > w ? (m.n_chunks - w + kWaves - 1) / kWaves : 0;
-    d4 acc_main[kMaxRound], acc_low[kMaxRound];
-#pragma unroll
-    for (int i = 0; i < kMaxRound; ++i) acc_main[i] = acc_low[i] = d4{0.0, 0.0, 0.0, 0.0};
+    const int nown = sc.n_own[w];
+    const int32_t* own = sc.own + w * kMaxOwn;
+    const int npdw = sc.n_pdw[w];
 
     const int64_t n_tiles = (n + kTile - 1) / kTile;
     for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
@@ -230,33 +227,24 @@ __global__ __launch_bounds__(kWaves * 64) void vjp_kernel(
         const double rc = rho[c];
         cs.lnT = log(cs.T);
         cs.invT = 1.0 / cs.T;
-        cs.invRT = cs.invT * (1.0 / kGasConstant);
-        cs.rtp = kGasConstant * cs.T / kOneAtm;
-        cs.irtp = 1.0 / cs.rtp;
         const double omlnT = 1.0 - cs.lnT;
 
-        // ---- species phase: C, G and wbar (zero for cells past n)
-        double y[MAXOWN];
-#pragma unroll
-        for (int i = 0; i < MAXOWN; ++i)
-            if (i < nown) y[i] = Y[size_t(own[i]) * ld + c];
+        // ---- species phase: C, G and wbar (zero for cells past n, so those
+        // lanes contribute nothing to any sum)
 #pragma unroll
         for (int i = 0; i < MAXOWN; ++i) {
             if (i < nown) {
                 const int k = own[i];
                 const SpeciesRec& s = m.species[k];
+                const double y = Y[size_t(k) * ld + c];
                 const double wb = valid ? wbar[size_t(k) * ld + c] : 0.0;
                 const double g_lo = gibbs_poly(s.lo, cs.T, omlnT, cs.invT);
                 const double g_hi = gibbs_poly(s.hi, cs.T, omlnT, cs.invT);
                 double* row = reinterpret_cast<double*>(lds + k * kVRow) + lane;
-                row[0] = rc * fmax(y[i], 0.0) * s.inv_w;
+                row[0] = rc * fmax(y, 0.0) * s.inv_w;
                 row[kTile] = exp(cs.T <= s.t_mid ? g_lo : g_hi);
                 row[2 * kTile] = wb;
             }
-        }
-        if (w == 0) {
-            fl[lane] = cs.lnT;
-            fl[kTile + lane] = -cs.invRT;
         }
         __syncthreads();
 
@@ -265,7 +253,7 @@ __global__ __launch_bounds__(kWaves * 64) void vjp_kernel(
 #pragma unroll
         for (int i = 0; i < MAXPD; ++i) Mr[i] = 0.0;
         if (npdw > 0) {
-            const double* ew = m.effw + size_t(w) * m.S * kMaxPd;
+            const double* ew = sc.effw + size_t(w) * m.S * kMaxPd;
             for (int k = 0; k < m.S; ++k) {
                 const double ck = reinterpret_cast<const double*>(lds + k * kVRow)[lane];
 #pragma unroll
@@ -278,82 +266,67 @@ __global__ __launch_bounds__(kWaves * 64) void vjp_kernel(
         for (int i = 0; i < MAXOWN; ++i) cc[i] = gam[i] = 0.0;
         double tbar = 0.0;
 
-        for (int ch = 0; ch < m.n_chunks; ++ch) {
-            const RxnRec* rb = m.rxn + (size_t(ch) * kWaves + w) * kRxnPerWave;
-#pragma unroll
-            for (int t = 0; t < kRxnPerWave; ++t) {
-                const RxnRec r = rb[t];
-                if (r.cls == kNoReaction) continue;
+        for (int ch = 0; ch < sc.n_chunks; ++ch) {
+            unsigned char* plane_a = bufs + (ch & 1) * kBuf;
+            unsigned char* plane_b = plane_a + kPlane;
+            const RxnRec r = sc.rxn[size_t(ch) * kVjpWaves + w];
+            if (r.cls != kNoReaction) {
                 const double M = r.cls >= kThirdBody ? pop_front(Mr) : 1.0;
                 const RevOut o = reaction_vjp(m, r, params, lds, lane, M, cs);
                 *reinterpret_cast<double*>(plane_a + r.qoff + lane * 8) = o.a;
                 *reinterpret_cast<double*>(plane_b + r.qoff + lane * 8) = o.b;
-                const int slot = r.qoff / (kTile * 8);
-                xT[lane * kXStride + slot] = o.xbar;
-                x0T[lane * kXStride + slot] = o.xbar0;
                 if (r.cls >= kThirdBody) mbar[size_t(r.pd) * kTile + lane] = o.Mbar;
                 tbar += o.Tbar;
-            }
-            if (w == 0) {
-                // empty slots of the chunk contribute nothing to the cell sums
-                const RxnRec* cb = m.rxn + size_t(ch) * kChunk;
-                for (int q = 0; q < kChunk; ++q)
-                    if (cb[q].cls == kNoReaction) {
-                        xT[lane * kXStride + q] = 0.0;
-                        x0T[lane * kXStride + q] = 0.0;
+                // cell sums of xbar (1, ln T, -1/(R T)) into this reaction's rows
+                const double s0 = wave_sum(o.xbar);
+                const double s1 = wave_sum(o.xbar * cs.lnT);
+                const double s2 = wave_sum(-o.xbar * cs.invRT());
+                double t0 = 0.0, t1 = 0.0, t2 = 0.0;
+                if (r.cls >= kLindemann) {
+                    t0 = wave_sum(o.xbar0);
+                    t1 = wave_sum(o.xbar0 * cs.lnT);
+                    t2 = wave_sum(-o.xbar0 * cs.invRT());
+                }
+                if (lane == 0) {
+                    double* pa = pacc + 3 * r.prow;
+                    pa[0] += s0;
+                    pa[1] += s1;
+                    pa[2] += s2;
+                    if (r.cls >= kLindemann) {
+                        double* pl = pacc + 3 * (m.R + r.fo);
+                        pl[0] += t0;
+                        pl[1] += t1;
+                        pl[2] += t2;
                     }
+                }
             }
             __syncthreads();
-            // species sums of this chunk
-            const int32_t* gp = m.vgptr + (size_t(ch) * kWaves + w) * (kMaxOwn + 1);
+            // species sums of this chunk (the next chunk fills the other buffer)
+            const int32_t* gp = sc.gptr + (size_t(ch) * kVjpWaves + w) * (kMaxOwn + 1);
             int32_t bound[MAXOWN + 1];
 #pragma unroll
             for (int i = 0; i <= MAXOWN; ++i) bound[i] = gp[i];
 #pragma unroll
             for (int i = 0; i < MAXOWN; ++i) {
                 if (i < nown) {
-                    double sc = cc[i], sg = gam[i];
+                    double sc_ = cc[i], sg = gam[i];
                     for (int e = bound[i]; e < bound[i + 1]; ++e) {
-                        const uint32_t g = m.vgent[e];
+                        const uint32_t g = sc.gent[e];
                         const int off = int(g & 0xffffu) + lane * 8;
                         const double av = *reinterpret_cast<const double*>(plane_a + off);
                         const double bv = *reinterpret_cast<const double*>(plane_b + off);
                         const double nf = double((g >> 16) & 0xffu), nr = double(g >> 24);
-                        sc = fma(nf, av, fma(-nr, bv, sc));
+                        sc_ = fma(nf, av, fma(-nr, bv, sc_));
                         sg = fma(nf - nr, bv, sg);
                     }
-                    cc[i] = sc;
+                    cc[i] = sc_;
                     gam[i] = sg;
                 }
             }
-            // cell sums of xbar (1, ln T, -1/(R T)) for this chunk's slots:
-            // D[f][slot] += sum_cells F[f][cell] xbar[cell][slot]
-            if (ch % kWaves == w) {
-                d4 dm = acc_main[0], dl = acc_low[0];
-                const int fr = lane & 15;
-                const bool low = m.chunk_fo[ch] != 0;
-#pragma unroll 4
-                for (int kk = 0; kk < kTile / 4; ++kk) {
-                    const int cl = 4 * kk + (lane >> 4);
-                    const double fa = fr == 0 ? 1.0 : fr == 1 ? fl[cl] : fr == 2 ? fl[kTile + cl] : 0.0;
-                    dm = __builtin_amdgcn_mfma_f64_16x16x4f64(fa, xT[cl * kXStride + fr], dm, 0, 0, 0);
-                    if (low)
-                        dl = __builtin_amdgcn_mfma_f64_16x16x4f64(fa, x0T[cl * kXStride + fr], dl, 0, 0, 0);
-                }
-                acc_main[0] = dm;
-                acc_low[0] = dl;
-                rotate(acc_main);
-                rotate(acc_low);
-            }
-            __syncthreads();
-        }
-        // keep every wave's accumulator queue in the same phase each tile
-        for (int i = my_rounds; i < kMaxRound; ++i) {
-            rotate(acc_main);
-            rotate(acc_low);
         }
 
-        // ---- species results
+        // ---- species results (every Mbar was written before the last
+        // chunk's barrier)
 #pragma unroll
         for (int i = 0; i < MAXOWN; ++i) {
             if (i < nown) {
@@ -361,7 +334,7 @@ __global__ __launch_bounds__(kWaves * 64) void vjp_kernel(
                 double cm = 0.0;  // sum_j eps_jk Mbar_j
                 const double* et = m.eff_t + size_t(k) * (m.n_pd > 0 ? m.n_pd : 1);
                 for (int j = 0; j < m.n_pd; ++j) cm = fma(et[j], mbar[size_t(j) * kTile + lane], cm);
-                const double yk = y[i];
+                const double yk = Y[size_t(k) * ld + c];
                 const double ybar = yk > 0.0 ? cc[i] / yk + rc * m.species[k].inv_w * cm : 0.0;
                 const NewtonSpecies& ns = m.newton[k];
                 const double h_lo = enthalpy_poly(ns.lo, cs.T, cs.invT);
@@ -370,52 +343,31 @@ __global__ __launch_bounds__(kWaves * 64) void vjp_kernel(
                 if (valid) Ybar[size_t(k) * ld + cell] = ybar;
             }
         }
-        // ---- temperature: per-wave partials summed in wave order
+        // ---- temperature: per-wave partials summed in wave order, staged in
+        // the chunk buffer the last chunk did not use
+        double* tb = reinterpret_cast<double*>(bufs + (sc.n_chunks & 1) * kBuf);
         tb[w * kTile + lane] = tbar;
         __syncthreads();
         if (w == 0) {
             double s = 0.0;
-            for (int v = 0; v < kWaves; ++v) s += tb[v * kTile + lane];
+            for (int v = 0; v < kVjpWaves; ++v) s += tb[v * kTile + lane];
             if (valid) Tbar[cell] = s;
         }
-        __syncthreads();
     }
-    // ---- per-workgroup partial sums: [block][chunk][plane][slot][f].  The
-    // MFMA result element D[f][slot] sits in lane 16 (f mod 4) + slot,
-    // register f / 4, so f = 0, 1, 2 are register 0 of lanes 0..47.
-    for (int i = 0; i < my_rounds; ++i) {
-        const int ch = w + i * kWaves;
-        const int f = lane >> 4;
-        if (f < 3) {
-            double* p = partial + ((size_t(blockIdx.x) * m.n_chunks + ch) * 2) * (kChunk * 3);
-            const int slot = lane & 15;
-            p[slot * 3 + f] = acc_main[0][0];
-            p[kChunk * 3 + slot * 3 + f] = acc_low[0][0];
-        }
-        rotate(acc_main);
-        rotate(acc_low);
-    }
+    // ---- this workgroup's parameter sums: [block][R + n_fo][3]
+    __syncthreads();
+    double* p = partial + size_t(blockIdx.x) * 3 * n_rows;
+    for (int i = threadIdx.x; i < 3 * n_rows; i += kVjpWaves * 64) p[i] = pacc[i];
 }
 
-// pbar[row][f] = sum over workgroups of the partials of the slot holding the
-// row's reaction, in workgroup order.
-__global__ void vjp_reduce_kernel(DevMech m, int blocks, const double* __restrict__ partial,
+// pbar[row][f] = sum over workgroups of their sums, in workgroup order.
+__global__ void vjp_reduce_kernel(int rows3, int blocks, const double* __restrict__ partial,
                                   double* __restrict__ pbar) {
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    const int total = m.n_chunks * 2 * kChunk * 3;
-    if (idx >= total) return;
-    const int f = idx % 3;
-    const int slot = (idx / 3) % kChunk;
-    const int plane = (idx / (3 * kChunk)) % 2;
-    const int ch = idx / (3 * kChunk * 2);
-    const RxnRec r = m.rxn[size_t(ch) * kChunk + slot];
-    if (r.cls == kNoReaction) return;
-    if (plane == 1 && r.cls < kLindemann) return;
-    const int row = plane == 0 ? r.prow : m.R + r.fo;
+    if (idx >= rows3) return;
     double s = 0.0;
-    const size_t stride = size_t(m.n_chunks) * 2 * kChunk * 3;
-    for (int b = 0; b < blocks; ++b) s += partial[size_t(b) * stride + idx];
-    pbar[size_t(row) * 3 + f] = s;
+    for (int b = 0; b < blocks; ++b) s += partial[size_t(b) * rows3 + idx];
+    pbar[idx] = s;
 }
 
 template <int MAXOWN, int MAXPD>
@@ -428,17 +380,39 @@ template <int MAXOWN, int MAXPD>
 hipError_t launch_vjp(const pyro_mech* m, int blocks, int64_t n, int64_t ld, const double* rho,
                       const double* T, const double* Y, const double* wbar, double* Ybar,
                       double* Tbar, double* partial, const double* params, hipStream_t stream) {
-    hipLaunchKernelGGL((vjp_kernel<MAXOWN, MAXPD>), dim3(unsigned(blocks)), dim3(kWaves * 64),
+    hipLaunchKernelGGL((vjp_kernel<MAXOWN, MAXPD>), dim3(unsigned(blocks)), dim3(kVjpWaves * 64),
                        vjp_lds_bytes(m), stream, m->dev, n, ld, rho, T, Y, wbar, Ybar, Tbar,
                        partial, params);
     return hipGetLastError();
 }
 
+template <int MAXOWN>
+hipError_t launch_vjp_own(const pyro_mech* m, int blocks, int64_t n, int64_t ld,
+                          const double* rho, const double* T, const double* Y, const double* wbar,
+                          double* Ybar, double* Tbar, double* partial, const double* params,
+                          hipStream_t stream) {
+    if (m->vjp_max_pdw <= 4)
+        return launch_vjp<MAXOWN, 4>(m, blocks, n, ld, rho, T, Y, wbar, Ybar, Tbar, partial, params, stream);
+    if (m->vjp_max_pdw <= 8)
+        return launch_vjp<MAXOWN, 8>(m, blocks, n, ld, rho, T, Y, wbar, Ybar, Tbar, partial, params, stream);
+    return launch_vjp<MAXOWN, 16>(m, blocks, n, ld, rho, T, Y, wbar, Ybar, Tbar, partial, params, stream);
+}
+
+template <int MAXOWN>
+hipError_t set_lds_own(int bytes) {
+    hipError_t e = hipSuccess;
+    const hipError_t all[] = {set_lds_vjp<MAXOWN, 4>(bytes), set_lds_vjp<MAXOWN, 8>(bytes),
+                              set_lds_vjp<MAXOWN, 16>(bytes)};
+    for (hipError_t x : all)
+        if (x != hipSuccess) e = x;
+    return e;
+}
+
 }  // namespace
 
 size_t vjp_lds_bytes(const pyro_mech* m) {
-    return size_t(m->S) * kVRow + kChunkBytes + size_t(m->n_tb + m->n_fo) * kTile * 8 +
-           2 * kTile * 8;
+    return size_t(m->S) * kVRow + 2 * kBuf + size_t(m->n_tb + m->n_fo) * kTile * 8 +
+           size_t(m->R + m->n_fo) * 3 * 8;
 }
 
 hipError_t prepare_vjp(const pyro_mech* m) {
@@ -446,8 +420,7 @@ hipError_t prepare_vjp(const pyro_mech* m) {
     if (bytes > 160 * 1024) return hipSuccess;  // the VJP call reports it as unsupported
     const int lds = int(bytes);
     hipError_t e = hipSuccess;
-    const hipError_t all[] = {set_lds_vjp<8, 8>(lds), set_lds_vjp<16, 8>(lds),
-                              set_lds_vjp<8, 16>(lds), set_lds_vjp<16, 16>(lds)};
+    const hipError_t all[] = {set_lds_own<4>(lds), set_lds_own<8>(lds), set_lds_own<16>(lds)};
     for (hipError_t x : all)
         if (x != hipSuccess) e = x;
     return e;
@@ -460,27 +433,23 @@ hipError_t launch_production_rates_vjp(const pyro_mech* m, int64_t n, int64_t ld
                                        hipStream_t stream) {
     const int64_t n_tiles = (n + kTile - 1) / kTile;
     const int blocks = int(std::min<int64_t>(n_tiles, int64_t(m->n_cu)));
-    const size_t pbytes = size_t(blocks) * m->dev.n_chunks * 2 * kChunk * 3 * sizeof(double);
+    const int rows3 = 3 * (m->R + m->n_fo);
+    const size_t pbytes = size_t(blocks) * rows3 * sizeof(double);
     void* partial = nullptr;
     hipError_t e = hipMallocAsync(&partial, pbytes > 0 ? pbytes : 8, stream);
     if (e != hipSuccess) return e;
     const double* pp = params ? params : m->dev.params;
     double* part = static_cast<double*>(partial);
-    if (m->max_own <= 8 && m->max_pdw <= 8)
-        e = launch_vjp<8, 8>(m, blocks, n, ld, rho, T, Y, wbar, Ybar, Tbar, part, pp, stream);
-    else if (m->max_own <= 16 && m->max_pdw <= 8)
-        e = launch_vjp<16, 8>(m, blocks, n, ld, rho, T, Y, wbar, Ybar, Tbar, part, pp, stream);
-    else if (m->max_own <= 8)
-        e = launch_vjp<8, 16>(m, blocks, n, ld, rho, T, Y, wbar, Ybar, Tbar, part, pp, stream);
+    if (m->vjp_max_own <= 4)
+        e = launch_vjp_own<4>(m, blocks, n, ld, rho, T, Y, wbar, Ybar, Tbar, part, pp, stream);
+    else if (m->vjp_max_own <= 8)
+        e = launch_vjp_own<8>(m, blocks, n, ld, rho, T, Y, wbar, Ybar, Tbar, part, pp, stream);
     else
-        e = launch_vjp<16, 16>(m, blocks, n, ld, rho, T, Y, wbar, Ybar, Tbar, part, pp, stream);
-    if (e == hipSuccess) {
-        const int total = m->dev.n_chunks * 2 * kChunk * 3;
-        if (total > 0) {
-            hipLaunchKernelGGL(vjp_reduce_kernel, dim3((total + 255) / 256), dim3(256), 0, stream,
-                               m->dev, blocks, part, params_bar);
-            e = hipGetLastError();
-        }
+        e = launch_vjp_own<16>(m, blocks, n, ld, rho, T, Y, wbar, Ybar, Tbar, part, pp, stream);
+    if (e == hipSuccess && rows3 > 0) {
+        hipLaunchKernelGGL(vjp_reduce_kernel, dim3((rows3 + 255) / 256), dim3(256), 0, stream,
+                           rows3, blocks, part, params_bar);
+        e = hipGetLastError();
     }
     const hipError_t ef = hipFreeAsync(partial, stream);
     return e != hipSuccess ? e : ef;

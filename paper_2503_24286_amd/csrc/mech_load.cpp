@@ -177,6 +177,155 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 }  // namespace
 
+struct SchedInput {
+    int S, R;
+    const std::vector<int32_t>* rtype;
+    const std::vector<int32_t>* rev;
+    const std::vector<std::vector<int>>* reac;
+    const std::vector<std::vector<int>>* prod;
+    const std::vector<int>* dnu;
+    const std::vector<int>* pd_row;
+    const std::vector<int>* fo_idx;
+    const std::vector<std::vector<std::pair<int, double>>>* by_species;
+};
+
+// A work schedule of one 64-cell tile over `waves` wavefronts: species
+// ownership (who gathers which species' sums, at most own_cap per wave) and
+// reactions dealt in chunks of waves * rpw slots, costliest first, each chunk
+// balanced over the waves.
+struct HostSched {
+    int waves = 0, rpw = 0, n_chunks = 0, max_own = 0, max_pdw = 0;
+    std::vector<RxnRec> recs;                    // [n_chunks][waves][rpw]
+    std::vector<std::vector<int>> own, pd_of_wave;
+    std::vector<int> slot_of, chunk_of;
+};
+
+int build_schedule(const SchedInput& in, int waves, int rpw, int own_cap, HostSched& out) {
+    const int S = in.S, R = in.R;
+    const auto& rtype = *in.rtype;
+    const auto& by_species = *in.by_species;
+    out.waves = waves;
+    out.rpw = rpw;
+    // species ownership: balance the gathering work over the waves
+    std::vector<int> order(S);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        return by_species[a].size() > by_species[b].size();
+    });
+    out.own.assign(waves, {});
+    std::vector<double> load(waves, 0.0);
+    for (int k : order) {
+        int best = -1;
+        for (int w = 0; w < waves; ++w)
+            if (int(out.own[w].size()) < own_cap && (best < 0 || load[w] < load[best])) best = w;
+        if (best < 0) return fail(PYRO_E_UNSUPPORTED, "too many species for one workgroup");
+        out.own[best].push_back(k);
+        load[best] += 2.0 + double(by_species[k].size());
+    }
+    for (auto& o : out.own) std::sort(o.begin(), o.end());
+    out.max_own = 0;
+    for (auto& o : out.own) out.max_own = std::max<int>(out.max_own, int(o.size()));
+
+    auto cost = [&](int j) {
+        double c = 1.0 + ((*in.rev)[j] ? 0.5 : 0.0);
+        if (rtype[j] >= 1) c += S / 24.0;
+        if (rtype[j] == 2) c += 1.5;
+        if (rtype[j] == 3) c += 6.0;
+        return c;
+    };
+    std::vector<int> rorder(R);
+    std::iota(rorder.begin(), rorder.end(), 0);
+    std::stable_sort(rorder.begin(), rorder.end(), [&](int a, int b) { return cost(a) > cost(b); });
+    const int chunk = waves * rpw;
+    out.n_chunks = (R + chunk - 1) / chunk;
+    out.recs.assign(size_t(std::max(out.n_chunks, 1)) * chunk, RxnRec{});
+    for (auto& r : out.recs) {
+        std::memset(&r, 0, sizeof(r));
+        r.cls = kNoReaction;
+    }
+    out.slot_of.assign(R, -1);
+    out.chunk_of.assign(R, -1);
+    out.pd_of_wave.assign(waves, {});
+    const int cg_stride = kTile * 16;  // bytes per species row of the C/G tile
+    for (int c = 0; c < out.n_chunks; ++c) {
+        std::vector<double> wl(waves, 0.0);
+        std::vector<int> used(waves, 0);
+        for (int t = c * chunk; t < std::min(R, (c + 1) * chunk); ++t) {
+            const int j = rorder[t];
+            const bool is_pd = rtype[j] >= 1;
+            int best = -1;
+            for (int w = 0; w < waves; ++w)
+                if (used[w] < rpw && !(is_pd && int(out.pd_of_wave[w].size()) == kMaxPd) &&
+                    (best < 0 || wl[w] < wl[best]))
+                    best = w;
+            if (best < 0) return fail(PYRO_E_UNSUPPORTED, "too many third-body and falloff reactions");
+            const int slot = best * rpw + used[best]++;
+            if (is_pd) out.pd_of_wave[best].push_back(j);
+            wl[best] += cost(j);
+            out.slot_of[j] = slot;
+            out.chunk_of[j] = c;
+            RxnRec& r = out.recs[size_t(c) * chunk + slot];
+            const auto& rj = (*in.reac)[j];
+            const auto& pj = (*in.prod)[j];
+            r.cls = rtype[j];
+            r.rev = (*in.rev)[j];
+            r.nr = int(rj.size());
+            r.np = int(pj.size());
+            for (int s = 0; s < kMaxSide; ++s) {
+                r.r[s] = s < r.nr ? rj[s] * cg_stride : 0;
+                r.p[s] = s < r.np ? pj[s] * cg_stride : 0;
+            }
+            r.dnu = (*in.dnu)[j];
+            r.prow = j;
+            r.pdw = is_pd ? int(out.pd_of_wave[best].size()) - 1 : -1;
+            r.fo = (*in.fo_idx)[j];
+            r.qoff = slot * kTile * 8;
+            r.pd = (*in.pd_row)[j];
+        }
+    }
+    out.max_pdw = 0;
+    for (auto& p : out.pd_of_wave) out.max_pdw = std::max<int>(out.max_pdw, int(p.size()));
+    return PYRO_OK;
+}
+
+// Gathering lists of a schedule: per (chunk, wave), kMaxOwn + 1 boundaries
+// into the entries that entries(k, chunk, out) appends for owned species k.
+template <typename F>
+void gather_lists(const HostSched& sc, F entries, std::vector<int32_t>& ptr,
+                  std::vector<uint32_t>& ent) {
+    ptr.reserve(size_t(std::max(sc.n_chunks, 1)) * sc.waves * (kMaxOwn + 1));
+    for (int c = 0; c < std::max(sc.n_chunks, 1); ++c)
+        for (int w = 0; w < sc.waves; ++w)
+            for (int i = 0; i <= kMaxOwn; ++i) {
+                ptr.push_back(int32_t(ent.size()));
+                if (i == kMaxOwn || i >= int(sc.own[w].size())) continue;
+                entries(sc.own[w][i], c, ent);
+            }
+    ent.resize(ent.size() + 2, 0u);  // slack: pairwise loops may read one past
+}
+
+// Per-wave tables of a schedule: efficiencies by (wave, species, wave slot),
+// so that the [M] pass of a wave reads the kMaxPd values of one species with
+// one scalar load, and the owned species.
+void wave_tables(const HostSched& sc, const std::vector<double>& eff,
+                 const std::vector<int>& pd_row, int S, std::vector<double>& effw,
+                 std::vector<int32_t>& n_pdw, std::vector<int32_t>& own_tab,
+                 std::vector<int32_t>& n_own) {
+    effw.assign(size_t(sc.waves) * S * kMaxPd, 0.0);
+    n_pdw.assign(sc.waves, 0);
+    own_tab.assign(size_t(sc.waves) * kMaxOwn, -1);
+    n_own.assign(sc.waves, 0);
+    for (int w = 0; w < sc.waves; ++w) {
+        n_pdw[w] = int(sc.pd_of_wave[w].size());
+        for (int i = 0; i < n_pdw[w]; ++i) {
+            const int row = pd_row[sc.pd_of_wave[w][i]];
+            for (int k = 0; k < S; ++k) effw[(size_t(w) * S + k) * kMaxPd + i] = eff[size_t(row) * S + k];
+        }
+        n_own[w] = int(sc.own[w].size());
+        for (size_t i = 0; i < sc.own[w].size(); ++i) own_tab[w * kMaxOwn + i] = sc.own[w][i];
+    }
+}
+
 int load_mechanism(const char* path, pyro_mech** out) {
     std::ifstream in(path, std::ios::binary);
     if (!in) return fail(PYRO_E_IO, std::string("cannot open ") + path);
@@ -233,134 +382,54 @@ int load_mechanism(const char* path, pyro_mech** out) {
         return fail(PYRO_E_UNSUPPORTED, "mechanism too large for the 64-cell LDS tile");
     }
 
-    // ---- species ownership: balance the gathering work over the waves
-    std::vector<int> order(S);
-    std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-        return by_species[a].size() > by_species[b].size();
-    });
-    std::vector<std::vector<int>> own(kWaves);
-    std::vector<double> load(kWaves, 0.0);
-    for (int k : order) {
-        int best = -1;
-        for (int w = 0; w < kWaves; ++w)
-            if (int(own[w].size()) < kMaxOwn && (best < 0 || load[w] < load[best])) best = w;
-        if (best < 0) {
-            delete m;
-            return fail(PYRO_E_UNSUPPORTED, "too many species for one workgroup");
-        }
-        own[best].push_back(k);
-        load[best] += 2.0 + double(by_species[k].size());
+    // ---- schedules: the forward kernel's (kWaves waves, kRxnPerWave
+    // reactions each per chunk) and the reverse sweep's (kVjpWaves, one each)
+    std::vector<std::vector<std::array<int, 3>>> part(S);  // species -> (j, nu', nu'')
+    for (int j = 0; j < R; ++j) {
+        std::vector<int> cf(S, 0), cr(S, 0);
+        for (int k : reac[j]) cf[k]++;
+        for (int k : prod[j]) cr[k]++;
+        for (int k = 0; k < S; ++k)
+            if (cf[k] || cr[k]) part[k].push_back({j, cf[k], cr[k]});
     }
-    for (auto& o : own) std::sort(o.begin(), o.end());
-    m->max_own = 0;
-    for (auto& o : own) m->max_own = std::max<int>(m->max_own, int(o.size()));
-
-    // ---- reaction schedule: chunks of kChunk, balanced over the waves
-    auto cost = [&](int j) {
-        double c = 1.0 + (f.rev[j] ? 0.5 : 0.0);
-        if (f.rtype[j] >= 1) c += S / 24.0;
-        if (f.rtype[j] == 2) c += 1.5;
-        if (f.rtype[j] == 3) c += 6.0;
-        return c;
-    };
-    std::vector<int> rorder(R);
-    std::iota(rorder.begin(), rorder.end(), 0);
-    std::stable_sort(rorder.begin(), rorder.end(), [&](int a, int b) { return cost(a) > cost(b); });
-    const int n_chunks = (R + kChunk - 1) / kChunk;
-    std::vector<RxnRec> recs(size_t(std::max(n_chunks, 1)) * kChunk);
-    for (auto& r : recs) {
-        std::memset(&r, 0, sizeof(r));
-        r.cls = kNoReaction;
+    const SchedInput sin{S, R, &f.rtype, &f.rev, &reac, &prod, &dnu, &pd_row, &fo_idx, &by_species};
+    HostSched fw, bw;
+    if (int rc = build_schedule(sin, kWaves, kRxnPerWave, kMaxOwn, fw)) {
+        delete m;
+        return rc;
     }
-    std::vector<int> slot_of(R, -1), chunk_of(R, -1), wave_of(R, -1);
-    std::vector<std::vector<int>> pd_of_wave(kWaves);
-    const int cg_stride = kTile * 16;  // bytes per species row of the C/G tile
-    for (int c = 0; c < n_chunks; ++c) {
-        std::vector<double> wl(kWaves, 0.0);
-        std::vector<int> used(kWaves, 0);
-        for (int t = c * kChunk; t < std::min(R, (c + 1) * kChunk); ++t) {
-            const int j = rorder[t];
-            const bool is_pd = f.rtype[j] >= 1;
-            int best = -1;
-            for (int w = 0; w < kWaves; ++w)
-                if (used[w] < kRxnPerWave && !(is_pd && int(pd_of_wave[w].size()) == kMaxPd) &&
-                    (best < 0 || wl[w] < wl[best]))
-                    best = w;
-            if (best < 0) {
-                delete m;
-                return fail(PYRO_E_UNSUPPORTED, "too many third-body and falloff reactions");
-            }
-            const int slot = best * kRxnPerWave + used[best]++;
-            wave_of[j] = best;
-            if (is_pd) pd_of_wave[best].push_back(j);
-            wl[best] += cost(j);
-            slot_of[j] = slot;
-            chunk_of[j] = c;
-            RxnRec& r = recs[size_t(c) * kChunk + slot];
-            r.cls = f.rtype[j];
-            r.rev = f.rev[j];
-            r.nr = int(reac[j].size());
-            r.np = int(prod[j].size());
-            for (int s = 0; s < kMaxSide; ++s) {
-                r.r[s] = s < r.nr ? reac[j][s] * cg_stride : 0;
-                r.p[s] = s < r.np ? prod[j][s] * cg_stride : 0;
-            }
-            r.dnu = dnu[j];
-            r.prow = j;
-            r.pdw = is_pd ? int(pd_of_wave[best].size()) - 1 : -1;
-            r.fo = fo_idx[j];
-            r.qoff = slot * kTile * 8;
-            r.pd = pd_row[j];
-        }
+    if (int rc = build_schedule(sin, kVjpWaves, 1,
+                           std::max(4, (S + kVjpWaves - 1) / kVjpWaves), bw)) {
+        delete m;
+        return rc;
     }
-    // ---- gathering lists: (chunk, wave, owned species) -> (slot, nu)
+    const int n_chunks = fw.n_chunks;
+    const std::vector<RxnRec>& recs = fw.recs;
+    m->max_own = fw.max_own;
+    m->max_pdw = fw.max_pdw;
+    m->vjp_max_own = bw.max_own;
+    m->vjp_max_pdw = bw.max_pdw;
+    // forward gathering lists: (chunk, wave, owned species) -> (slot, nu).
     // gptr holds, per (chunk, wave), kMaxOwn + 1 boundaries: the entries of
     // owned species i span [gptr[base + i], gptr[base + i + 1]).
     std::vector<int32_t> gptr;
     std::vector<GatherEntry> gent;
-    gptr.reserve(size_t(std::max(n_chunks, 1)) * kWaves * (kMaxOwn + 1));
-    for (int c = 0; c < std::max(n_chunks, 1); ++c)
-        for (int w = 0; w < kWaves; ++w)
-            for (int i = 0; i <= kMaxOwn; ++i) {
-                gptr.push_back(int32_t(gent.size()));
-                if (i == kMaxOwn || i >= int(own[w].size())) continue;
-                for (auto& e : by_species[own[w][i]])
-                    if (chunk_of[e.first] == c) {
-                        const uint32_t qoff = uint32_t(slot_of[e.first] * kTile * 8);
-                        const int nu = int(e.second);
-                        gent.push_back(qoff | (uint32_t(uint16_t(int16_t(nu))) << 16));
-                    }
+    gather_lists(fw, [&](int k, int c, std::vector<uint32_t>& out) {
+        for (auto& e : by_species[k])
+            if (fw.chunk_of[e.first] == c) {
+                const uint32_t qoff = uint32_t(fw.slot_of[e.first] * kTile * 8);
+                out.push_back(qoff | (uint32_t(uint16_t(int16_t(int(e.second)))) << 16));
             }
-    gent.resize(gent.size() + 2, 0u);  // slack: the pairwise loop may read one past
-
-    // ---- reverse-sweep gathering lists: per participant (slot, nu', nu'')
+    }, gptr, gent);
+    // reverse-sweep gathering lists: per participant (slot, nu', nu'')
     std::vector<int32_t> vgptr;
     std::vector<uint32_t> vgent;
-    {
-        std::vector<std::vector<std::array<int, 3>>> part(S);  // species -> (j, nu', nu'')
-        for (int j = 0; j < R; ++j) {
-            std::vector<int> cf(S, 0), cr(S, 0);
-            for (int k : reac[j]) cf[k]++;
-            for (int k : prod[j]) cr[k]++;
-            for (int k = 0; k < S; ++k)
-                if (cf[k] || cr[k]) part[k].push_back({j, cf[k], cr[k]});
-        }
-        for (int c = 0; c < std::max(n_chunks, 1); ++c)
-            for (int w = 0; w < kWaves; ++w)
-                for (int i = 0; i <= kMaxOwn; ++i) {
-                    vgptr.push_back(int32_t(vgent.size()));
-                    if (i == kMaxOwn || i >= int(own[w].size())) continue;
-                    for (auto& e : part[own[w][i]])
-                        if (chunk_of[e[0]] == c)
-                            vgent.push_back(uint32_t(slot_of[e[0]] * kTile * 8) |
-                                            (uint32_t(e[1]) << 16) | (uint32_t(e[2]) << 24));
-                }
-        vgent.resize(vgent.size() + 2, 0u);
-    }
-    std::vector<int32_t> chunk_fo(std::max(n_chunks, 1), 0);
-    for (int j = 0; j < R; ++j)
-        if (f.rtype[j] >= 2) chunk_fo[chunk_of[j]] = 1;
+    gather_lists(bw, [&](int k, int c, std::vector<uint32_t>& out) {
+        for (auto& e : part[k])
+            if (bw.chunk_of[e[0]] == c)
+                out.push_back(uint32_t(bw.slot_of[e[0]] * kTile * 8) | (uint32_t(e[1]) << 16) |
+                              (uint32_t(e[2]) << 24));
+    }, vgptr, vgent);
     std::vector<double> comp_d(f.comp.begin(), f.comp.end());
     if (comp_d.empty()) comp_d.push_back(0.0);
     std::vector<double> eff_t(size_t(S) * std::max(n_pd, 1), 0.0);
@@ -411,25 +480,10 @@ int load_mechanism(const char* path, pyro_mech** out) {
         fr[i].a2 = -t[3];
     }
     const int s_pad = (S + 7) / 8 * 8;
-    // efficiencies by (wave, species, wave slot): the [M] pass of a wave
-    // reads the kMaxPd values of one species with one scalar load
-    std::vector<double> effw(size_t(kWaves) * S * kMaxPd, 0.0);
-    std::vector<int32_t> n_pdw(kWaves, 0);
-    m->max_pdw = 0;
-    for (int w = 0; w < kWaves; ++w) {
-        n_pdw[w] = int(pd_of_wave[w].size());
-        m->max_pdw = std::max(m->max_pdw, n_pdw[w]);
-        for (int i = 0; i < n_pdw[w]; ++i) {
-            const int row = pd_row[pd_of_wave[w][i]];
-            for (int k = 0; k < S; ++k)
-                effw[(size_t(w) * S + k) * kMaxPd + i] = f.eff[size_t(row) * S + k];
-        }
-    }
-    std::vector<int32_t> own_tab(kWaves * kMaxOwn, -1), n_own(kWaves);
-    for (int w = 0; w < kWaves; ++w) {
-        n_own[w] = int(own[w].size());
-        for (size_t i = 0; i < own[w].size(); ++i) own_tab[w * kMaxOwn + i] = own[w][i];
-    }
+    std::vector<double> effw, veffw;
+    std::vector<int32_t> n_pdw, vn_pdw, own_tab, n_own, vown_tab, vn_own;
+    wave_tables(fw, f.eff, pd_row, S, effw, n_pdw, own_tab, n_own);
+    wave_tables(bw, f.eff, pd_row, S, veffw, vn_pdw, vown_tab, vn_own);
     std::vector<double> params = m->params;
     if (params.empty()) params.push_back(0.0);
 
@@ -451,8 +505,12 @@ int load_mechanism(const char* path, pyro_mech** out) {
         {vgptr.data(), vgptr.size() * sizeof(int32_t), 0},
         {vgent.data(), vgent.size() * sizeof(uint32_t), 0},
         {eff_t.data(), eff_t.size() * sizeof(double), 0},
-        {chunk_fo.data(), chunk_fo.size() * sizeof(int32_t), 0},
+        {bw.recs.data(), bw.recs.size() * sizeof(RxnRec), 0},
         {comp_d.data(), comp_d.size() * sizeof(double), 0},
+        {veffw.data(), veffw.size() * sizeof(double), 0},
+        {vn_pdw.data(), vn_pdw.size() * sizeof(int32_t), 0},
+        {vown_tab.data(), vown_tab.size() * sizeof(int32_t), 0},
+        {vn_own.data(), vn_own.size() * sizeof(int32_t), 0},
     };
     size_t total = 0;
     for (auto& p : parts) {
@@ -505,12 +563,18 @@ int load_mechanism(const char* path, pyro_mech** out) {
     d.gent = reinterpret_cast<const GatherEntry*>(base + parts[9].off);
     d.newton = reinterpret_cast<const NewtonSpecies*>(base + parts[10].off);
     d.w = reinterpret_cast<const double*>(base + parts[11].off);
-    d.vgptr = reinterpret_cast<const int32_t*>(base + parts[12].off);
-    d.vgent = reinterpret_cast<const uint32_t*>(base + parts[13].off);
     d.eff_t = reinterpret_cast<const double*>(base + parts[14].off);
-    d.chunk_fo = reinterpret_cast<const int32_t*>(base + parts[15].off);
     d.E = int(f.E);
     d.comp = reinterpret_cast<const double*>(base + parts[16].off);
+    DevSched& v = d.vjp;
+    v.n_chunks = bw.n_chunks;
+    v.rxn = reinterpret_cast<const RxnRec*>(base + parts[15].off);
+    v.gptr = reinterpret_cast<const int32_t*>(base + parts[12].off);
+    v.gent = reinterpret_cast<const uint32_t*>(base + parts[13].off);
+    v.effw = reinterpret_cast<const double*>(base + parts[17].off);
+    v.n_pdw = reinterpret_cast<const int32_t*>(base + parts[18].off);
+    v.own = reinterpret_cast<const int32_t*>(base + parts[19].off);
+    v.n_own = reinterpret_cast<const int32_t*>(base + parts[20].off);
     err = prepare_production_rates(m);
     if (err == hipSuccess) err = prepare_vjp(m);
     if (err != hipSuccess) {

@@ -34,6 +34,7 @@ constexpr int kMaxPd = 16;
 constexpr int kMaxSide = 3;
 // Max distinct T_mid values among the species (Newton kernel groups).
 constexpr int kMaxTmidGroups = 4;
+constexpr int kVjpWaves = 16;            // wavefronts of the reverse-sweep workgroup
 
 // Reaction classes.
 enum : int32_t { kElementary = 0, kThirdBody = 1, kLindemann = 2, kTroe = 3,
@@ -93,6 +94,20 @@ struct NewtonSpecies {
 static_assert(sizeof(NewtonSpecies) == 128, "NewtonSpecies must be 128 bytes");
 
 // Device-side view of a mechanism, passed to kernels by value.
+// The tables of one work schedule (see the loader): chunks of waves x rpw
+// reaction slots, species owned per wave, gathering lists.
+struct DevSched {
+    int32_t n_chunks;
+    int32_t pad;
+    const RxnRec* rxn;                   // [n_chunks][waves][rpw]
+    const double* effw;                  // [waves][S][kMaxPd] efficiencies by wave slot
+    const int32_t* n_pdw;                // [waves]
+    const int32_t* own;                  // [waves][kMaxOwn]
+    const int32_t* n_own;                // [waves]
+    const int32_t* gptr;                 // [n_chunks][waves][kMaxOwn + 1]
+    const uint32_t* gent;                // reverse sweep: slot offset | nu' << 16 | nu'' << 24
+};
+
 struct DevMech {
     int32_t S, R, n_pd, n_fo;
     int32_t n_chunks;
@@ -112,11 +127,9 @@ struct DevMech {
     const GatherEntry* gent;             // gathering entries
     const NewtonSpecies* newton;         // [S]
     const double* w;                     // [S] molar masses
-    // reverse sweep (VJP)
-    const int32_t* vgptr;                // [n_chunks][kWaves][kMaxOwn + 1]
-    const uint32_t* vgent;               // slot offset | nu' << 16 | nu'' << 24
+    // reverse sweep (VJP): its own schedule over kVjpWaves wavefronts
+    DevSched vjp;
     const double* eff_t;                 // [S][n_pd] efficiencies by species
-    const int32_t* chunk_fo;             // [n_chunks] 1 if the chunk holds a falloff reaction
     // surrogate
     int32_t E;                           // elements
     int32_t pad2;
@@ -131,6 +144,8 @@ struct pyro_mech {
     int nnz_f = 0, nnz_r = 0, nnz_net = 0;
     int max_own = 0;
     int max_pdw = 0;
+    int vjp_max_own = 0;                 // the same for the reverse-sweep schedule
+    int vjp_max_pdw = 0;
     int n_cu = 0;                        // compute units of the device
     std::vector<double> W;               // host copy
     std::vector<double> params;          // host copy of the default triples
