@@ -189,10 +189,27 @@ __device__ inline RevOut reaction_vjp(const DevMech& m, const RxnRec& r,
     return o;
 }
 
-// sum over the 64 lanes, bitwise identical in every lane and run
+// one DPP move of a double (both halves with the same control)
+template <int CTRL, int ROW_MASK>
+__device__ inline double dpp(double v) {
+    const int2 h = __builtin_bit_cast(int2, v);
+    int2 r;
+    r.x = __builtin_amdgcn_update_dpp(0, h.x, CTRL, ROW_MASK, 0xf, false);
+    r.y = __builtin_amdgcn_update_dpp(0, h.y, CTRL, ROW_MASK, 0xf, false);
+    return __builtin_bit_cast(double, r);
+}
+
+// Sum over the 64 lanes with DPP row operations (no LDS traffic), in a fixed
+// order; the total lands in lane 63.  Quads, half rows and rows are summed
+// with quad permutations and mirrors; row 15's total is broadcast into rows
+// 1 and 3, then lane 31's into rows 2 and 3.
 __device__ inline double wave_sum(double v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    v += dpp<0xb1, 0xf>(v);    // quad_perm [1, 0, 3, 2]
+    v += dpp<0x4e, 0xf>(v);    // quad_perm [2, 3, 0, 1]
+    v += dpp<0x141, 0xf>(v);   // row_half_mirror
+    v += dpp<0x140, 0xf>(v);   // row_mirror
+    v += dpp<0x142, 0xa>(v);   // row_bcast:15 into rows 1 and 3
+    v += dpp<0x143, 0xc>(v);   // row_bcast:31 into rows 2 and 3
     return v;
 }
 
@@ -254,7 +271,19 @@ __global__ __launch_bounds__(kVjpWaves * 64) void vjp_kernel(
         for (int i = 0; i < MAXPD; ++i) Mr[i] = 0.0;
         if (npdw > 0) {
             const double* ew = sc.effw + size_t(w) * m.S * kMaxPd;
-            for (int k = 0; k < m.S; ++k) {
+            int k = 0;
+            for (; k + 4 <= m.S; k += 4) {
+                double ck[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    ck[u] = reinterpret_cast<const double*>(lds + (k + u) * kVRow)[lane];
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+#pragma unroll
+                    for (int i = 0; i < MAXPD; ++i)
+                        Mr[i] = fma(ew[(k + u) * kMaxPd + i], ck[u], Mr[i]);
+            }
+            for (; k < m.S; ++k) {
                 const double ck = reinterpret_cast<const double*>(lds + k * kVRow)[lane];
 #pragma unroll
                 for (int i = 0; i < MAXPD; ++i) Mr[i] = fma(ew[k * kMaxPd + i], ck, Mr[i]);
@@ -287,7 +316,7 @@ __global__ __launch_bounds__(kVjpWaves * 64) void vjp_kernel(
                     t1 = wave_sum(o.xbar0 * cs.lnT);
                     t2 = wave_sum(-o.xbar0 * cs.invRT());
                 }
-                if (lane == 0) {
+                if (lane == 63) {
                     double* pa = pacc + 3 * r.prow;
                     pa[0] += s0;
                     pa[1] += s1;
@@ -309,18 +338,34 @@ __global__ __launch_bounds__(kVjpWaves * 64) void vjp_kernel(
 #pragma unroll
             for (int i = 0; i < MAXOWN; ++i) {
                 if (i < nown) {
-                    double sc_ = cc[i], sg = gam[i];
-                    for (int e = bound[i]; e < bound[i + 1]; ++e) {
+                    // two entries per step, their loads issued together
+                    double sc0 = cc[i], sg0 = gam[i], sc1 = 0.0, sg1 = 0.0;
+                    int e = bound[i];
+                    for (; e + 1 < bound[i + 1]; e += 2) {
+                        const uint32_t g0 = sc.gent[e], g1 = sc.gent[e + 1];
+                        const int o0 = int(g0 & 0xffffu) + lane * 8, o1 = int(g1 & 0xffffu) + lane * 8;
+                        const double a0 = *reinterpret_cast<const double*>(plane_a + o0);
+                        const double b0 = *reinterpret_cast<const double*>(plane_b + o0);
+                        const double a1 = *reinterpret_cast<const double*>(plane_a + o1);
+                        const double b1 = *reinterpret_cast<const double*>(plane_b + o1);
+                        const double f0 = double((g0 >> 16) & 0xffu), r0 = double(g0 >> 24);
+                        const double f1 = double((g1 >> 16) & 0xffu), r1 = double(g1 >> 24);
+                        sc0 = fma(f0, a0, fma(-r0, b0, sc0));
+                        sg0 = fma(f0 - r0, b0, sg0);
+                        sc1 = fma(f1, a1, fma(-r1, b1, sc1));
+                        sg1 = fma(f1 - r1, b1, sg1);
+                    }
+                    if (e < bound[i + 1]) {
                         const uint32_t g = sc.gent[e];
                         const int off = int(g & 0xffffu) + lane * 8;
                         const double av = *reinterpret_cast<const double*>(plane_a + off);
                         const double bv = *reinterpret_cast<const double*>(plane_b + off);
                         const double nf = double((g >> 16) & 0xffu), nr = double(g >> 24);
-                        sc_ = fma(nf, av, fma(-nr, bv, sc_));
-                        sg = fma(nf - nr, bv, sg);
+                        sc0 = fma(nf, av, fma(-nr, bv, sc0));
+                        sg0 = fma(nf - nr, bv, sg0);
                     }
-                    cc[i] = sc_;
-                    gam[i] = sg;
+                    cc[i] = sc0 + sc1;
+                    gam[i] = sg0 + sg1;
                 }
             }
         }
@@ -333,7 +378,18 @@ __global__ __launch_bounds__(kVjpWaves * 64) void vjp_kernel(
                 const int k = own[i];
                 double cm = 0.0;  // sum_j eps_jk Mbar_j
                 const double* et = m.eff_t + size_t(k) * (m.n_pd > 0 ? m.n_pd : 1);
-                for (int j = 0; j < m.n_pd; ++j) cm = fma(et[j], mbar[size_t(j) * kTile + lane], cm);
+                {
+                    double c1 = 0.0, c2 = 0.0, c3 = 0.0;
+                    int j = 0;
+                    for (; j + 4 <= m.n_pd; j += 4) {
+                        cm = fma(et[j], mbar[size_t(j) * kTile + lane], cm);
+                        c1 = fma(et[j + 1], mbar[size_t(j + 1) * kTile + lane], c1);
+                        c2 = fma(et[j + 2], mbar[size_t(j + 2) * kTile + lane], c2);
+                        c3 = fma(et[j + 3], mbar[size_t(j + 3) * kTile + lane], c3);
+                    }
+                    for (; j < m.n_pd; ++j) cm = fma(et[j], mbar[size_t(j) * kTile + lane], cm);
+                    cm += (c1 + c2) + c3;
+                }
                 const double yk = Y[size_t(k) * ld + c];
                 const double ybar = yk > 0.0 ? cc[i] / yk + rc * m.species[k].inv_w * cm : 0.0;
                 const NewtonSpecies& ns = m.newton[k];
