@@ -255,6 +255,9 @@ def main():
     ap.add_argument("--reps", type=int, default=10)
     ap.add_argument("--threads", type=int, default=16)
     ap.add_argument("--targets", type=float, nargs="+", default=[1e-3, 1e-2, 1e-1])
+    ap.add_argument("--calibration-copy", type=int, default=0, metavar="MIB",
+                    help="end with one plain device-to-device copy of MIB MiB (a kernel of "
+                         "known traffic for scaling hardware byte counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -370,6 +373,12 @@ def main():
         def log(msg):
             print(f"# {msg}", file=sys.stderr, flush=True)
         result["surrogate"] = surrogate_leg(args, log)
+    if args.calibration_copy > 0:
+        src = torch.empty(args.calibration_copy << 17, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(args.cpu_sample, max(args.cpu_sample // 64, 64))
     print(json.dumps(result), flush=True)

@@ -200,7 +200,8 @@ struct HostSched {
     std::vector<int> slot_of, chunk_of;
 };
 
-int build_schedule(const SchedInput& in, int waves, int rpw, int own_cap, HostSched& out) {
+int build_schedule(const SchedInput& in, int waves, int rpw, int own_cap,
+                   const std::vector<std::vector<int>>& gathered, HostSched& out) {
     const int S = in.S, R = in.R;
     const auto& rtype = *in.rtype;
     const auto& by_species = *in.by_species;
@@ -238,6 +239,47 @@ int build_schedule(const SchedInput& in, int waves, int rpw, int own_cap, HostSc
     std::stable_sort(rorder.begin(), rorder.end(), [&](int a, int b) { return cost(a) > cost(b); });
     const int chunk = waves * rpw;
     out.n_chunks = (R + chunk - 1) / chunk;
+    // chunk membership: by cost rank, then pairwise swaps of reactions of the
+    // same cost class between chunks while they lower the sum over chunks of
+    // the largest per-wave gathering load (each chunk ends at a barrier)
+    std::vector<int> chunk_of(R);
+    for (int t = 0; t < R; ++t) chunk_of[rorder[t]] = t / chunk;
+    std::vector<int> owner(S, 0);
+    for (int w = 0; w < waves; ++w)
+        for (int k : out.own[w]) owner[k] = w;
+    std::vector<std::vector<int>> contrib(R, std::vector<int>(waves, 0));
+    for (int j = 0; j < R; ++j)
+        for (int k : gathered[j]) contrib[j][owner[k]]++;
+    std::vector<std::vector<int>> load_cw(std::max(out.n_chunks, 1), std::vector<int>(waves, 0));
+    for (int j = 0; j < R; ++j)
+        for (int w = 0; w < waves; ++w) load_cw[chunk_of[j]][w] += contrib[j][w];
+    auto max_after = [&](int c, int rm, int add) {
+        int mx = 0;
+        for (int w = 0; w < waves; ++w)
+            mx = std::max(mx, load_cw[c][w] - contrib[rm][w] + contrib[add][w]);
+        return mx;
+    };
+    auto cmax = [&](int c) { return *std::max_element(load_cw[c].begin(), load_cw[c].end()); };
+    auto same_class = [&](int a, int b) { return rtype[a] == rtype[b] && (*in.rev)[a] == (*in.rev)[b]; };
+    for (int sweep = 0; sweep < 8; ++sweep) {
+        bool improved = false;
+        for (int a = 0; a < R; ++a)
+            for (int b = a + 1; b < R; ++b) {
+                const int ca = chunk_of[a], cb = chunk_of[b];
+                if (ca == cb || !same_class(a, b)) continue;
+                const int delta = max_after(ca, a, b) + max_after(cb, b, a) - cmax(ca) - cmax(cb);
+                if (delta >= 0) continue;
+                for (int w = 0; w < waves; ++w) {
+                    load_cw[ca][w] += contrib[b][w] - contrib[a][w];
+                    load_cw[cb][w] += contrib[a][w] - contrib[b][w];
+                }
+                std::swap(chunk_of[a], chunk_of[b]);
+                improved = true;
+            }
+        if (!improved) break;
+    }
+    std::vector<std::vector<int>> members(std::max(out.n_chunks, 1));
+    for (int t = 0; t < R; ++t) members[chunk_of[rorder[t]]].push_back(rorder[t]);
     out.recs.assign(size_t(std::max(out.n_chunks, 1)) * chunk, RxnRec{});
     for (auto& r : out.recs) {
         std::memset(&r, 0, sizeof(r));
@@ -250,8 +292,7 @@ int build_schedule(const SchedInput& in, int waves, int rpw, int own_cap, HostSc
     for (int c = 0; c < out.n_chunks; ++c) {
         std::vector<double> wl(waves, 0.0);
         std::vector<int> used(waves, 0);
-        for (int t = c * chunk; t < std::min(R, (c + 1) * chunk); ++t) {
-            const int j = rorder[t];
+        for (int j : members[c]) {
             const bool is_pd = rtype[j] >= 1;
             int best = -1;
             for (int w = 0; w < waves; ++w)
@@ -393,13 +434,20 @@ int load_mechanism(const char* path, pyro_mech** out) {
             if (cf[k] || cr[k]) part[k].push_back({j, cf[k], cr[k]});
     }
     const SchedInput sin{S, R, &f.rtype, &f.rev, &reac, &prod, &dnu, &pd_row, &fo_idx, &by_species};
+    // species each kernel's gathering visits per reaction: net coefficient
+    // for the forward sums, any participation for the reverse sweep
+    std::vector<std::vector<int>> g_net(R), g_part(R);
+    for (int k = 0; k < S; ++k) {
+        for (auto& e : by_species[k]) g_net[e.first].push_back(k);
+        for (auto& e : part[k]) g_part[e[0]].push_back(k);
+    }
     HostSched fw, bw;
-    if (int rc = build_schedule(sin, kWaves, kRxnPerWave, kMaxOwn, fw)) {
+    if (int rc = build_schedule(sin, kWaves, kRxnPerWave, kMaxOwn, g_net, fw)) {
         delete m;
         return rc;
     }
-    if (int rc = build_schedule(sin, kVjpWaves, 1,
-                           std::max(4, (S + kVjpWaves - 1) / kVjpWaves), bw)) {
+    if (int rc = build_schedule(sin, kVjpWaves, 1, std::max(4, (S + kVjpWaves - 1) / kVjpWaves),
+                                g_part, bw)) {
         delete m;
         return rc;
     }
