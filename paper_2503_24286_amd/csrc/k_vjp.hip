@@ -87,18 +87,18 @@ __device__ inline RevOut reaction_vjp(const DevMech& m, const RxnRec& r,
                                       const double* __restrict__ params,
                                       const unsigned char* lds, int lane, double M,
                                       const CellState& cs) {
-    const double* pr = params + 3 * r.prow;
+    const cptr<double> pr = cst(params) + 3 * r.prow;
     const double kinf = exp(fma(-pr[2], cs.invRT(), fma(pr[1], cs.lnT, pr[0])));
     const double dxdT = fma(pr[2] * cs.invRT(), cs.invT, pr[1] * cs.invT);
     double keff = kinf, s = 0.0, dlnF_dT = 0.0, k0 = 0.0, F = 1.0, Pr = 0.0;
     double dlnF_dlnPr = 0.0, dx0dT = 0.0;
     if (r.cls >= kLindemann) {
-        const double* pl = params + 3 * (m.R + r.fo);
+        const cptr<double> pl = cst(params) + 3 * (m.R + r.fo);
         k0 = exp(fma(-pl[2], cs.invRT(), fma(pl[1], cs.lnT, pl[0])));
         dx0dT = fma(pl[2] * cs.invRT(), cs.invT, pl[1] * cs.invT);
         Pr = k0 * M / kinf;
         if (r.cls == kTroe) {
-            const FalloffRec f = m.falloff[r.fo];
+            const FalloffRec f = cst(m.falloff)[r.fo];
             const double e3 = exp(cs.T * f.a3), e1 = exp(cs.T * f.a1), e2 = exp(f.a2 * cs.invT);
             const double Fc_raw = (1.0 - f.alpha) * e3 + f.alpha * e1 + e2;
             const bool fc_ok = Fc_raw > 1e-300;
@@ -230,9 +230,9 @@ __global__ __launch_bounds__(kVjpWaves * 64) void vjp_kernel(
     const int n_rows = m.R + m.n_fo;
     for (int i = threadIdx.x; i < 3 * n_rows; i += kVjpWaves * 64) pacc[i] = 0.0;
 
-    const int nown = sc.n_own[w];
-    const int32_t* own = sc.own + w * kMaxOwn;
-    const int npdw = sc.n_pdw[w];
+    const int nown = cst(sc.n_own)[w];
+    const cptr<int32_t> own = cst(sc.own) + w * kMaxOwn;
+    const int npdw = cst(sc.n_pdw)[w];
 
     const int64_t n_tiles = (n + kTile - 1) / kTile;
     for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
@@ -252,7 +252,7 @@ __global__ __launch_bounds__(kVjpWaves * 64) void vjp_kernel(
         for (int i = 0; i < MAXOWN; ++i) {
             if (i < nown) {
                 const int k = own[i];
-                const SpeciesRec& s = m.species[k];
+                const SpeciesRec s = cst(m.species)[k];
                 const double y = Y[size_t(k) * ld + c];
                 const double wb = valid ? wbar[size_t(k) * ld + c] : 0.0;
                 const double g_lo = gibbs_poly(s.lo, cs.T, omlnT, cs.invT);
@@ -270,7 +270,7 @@ __global__ __launch_bounds__(kVjpWaves * 64) void vjp_kernel(
 #pragma unroll
         for (int i = 0; i < MAXPD; ++i) Mr[i] = 0.0;
         if (npdw > 0) {
-            const double* ew = sc.effw + size_t(w) * m.S * kMaxPd;
+            const cptr<double> ew = cst(sc.effw) + size_t(w) * m.S * kMaxPd;
             int k = 0;
             for (; k + 4 <= m.S; k += 4) {
                 double ck[4];
@@ -298,7 +298,7 @@ __global__ __launch_bounds__(kVjpWaves * 64) void vjp_kernel(
         for (int ch = 0; ch < sc.n_chunks; ++ch) {
             unsigned char* plane_a = bufs + (ch & 1) * kBuf;
             unsigned char* plane_b = plane_a + kPlane;
-            const RxnRec r = sc.rxn[size_t(ch) * kVjpWaves + w];
+            const RxnRec r = cst(sc.rxn)[size_t(ch) * kVjpWaves + w];
             if (r.cls != kNoReaction) {
                 const double M = r.cls >= kThirdBody ? pop_front(Mr) : 1.0;
                 const RevOut o = reaction_vjp(m, r, params, lds, lane, M, cs);
@@ -331,7 +331,8 @@ __global__ __launch_bounds__(kVjpWaves * 64) void vjp_kernel(
             }
             __syncthreads();
             // species sums of this chunk (the next chunk fills the other buffer)
-            const int32_t* gp = sc.gptr + (size_t(ch) * kVjpWaves + w) * (kMaxOwn + 1);
+            const cptr<int32_t> gp = cst(sc.gptr) + (size_t(ch) * kVjpWaves + w) * (kMaxOwn + 1);
+            const cptr<uint32_t> gent = cst(sc.gent);
             int32_t bound[MAXOWN + 1];
 #pragma unroll
             for (int i = 0; i <= MAXOWN; ++i) bound[i] = gp[i];
@@ -342,7 +343,7 @@ __global__ __launch_bounds__(kVjpWaves * 64) void vjp_kernel(
                     double sc0 = cc[i], sg0 = gam[i], sc1 = 0.0, sg1 = 0.0;
                     int e = bound[i];
                     for (; e + 1 < bound[i + 1]; e += 2) {
-                        const uint32_t g0 = sc.gent[e], g1 = sc.gent[e + 1];
+                        const uint32_t g0 = gent[e], g1 = gent[e + 1];
                         const int o0 = int(g0 & 0xffffu) + lane * 8, o1 = int(g1 & 0xffffu) + lane * 8;
                         const double a0 = *reinterpret_cast<const double*>(plane_a + o0);
                         const double b0 = *reinterpret_cast<const double*>(plane_b + o0);
@@ -356,7 +357,7 @@ __global__ __launch_bounds__(kVjpWaves * 64) void vjp_kernel(
                         sg1 = fma(f1 - r1, b1, sg1);
                     }
                     if (e < bound[i + 1]) {
-                        const uint32_t g = sc.gent[e];
+                        const uint32_t g = gent[e];
                         const int off = int(g & 0xffffu) + lane * 8;
                         const double av = *reinterpret_cast<const double*>(plane_a + off);
                         const double bv = *reinterpret_cast<const double*>(plane_b + off);
@@ -377,7 +378,7 @@ __global__ __launch_bounds__(kVjpWaves * 64) void vjp_kernel(
             if (i < nown) {
                 const int k = own[i];
                 double cm = 0.0;  // sum_j eps_jk Mbar_j
-                const double* et = m.eff_t + size_t(k) * (m.n_pd > 0 ? m.n_pd : 1);
+                const cptr<double> et = cst(m.eff_t) + size_t(k) * (m.n_pd > 0 ? m.n_pd : 1);
                 {
                     double c1 = 0.0, c2 = 0.0, c3 = 0.0;
                     int j = 0;
@@ -391,11 +392,12 @@ __global__ __launch_bounds__(kVjpWaves * 64) void vjp_kernel(
                     cm += (c1 + c2) + c3;
                 }
                 const double yk = Y[size_t(k) * ld + c];
-                const double ybar = yk > 0.0 ? cc[i] / yk + rc * m.species[k].inv_w * cm : 0.0;
-                const NewtonSpecies& ns = m.newton[k];
+                const SpeciesRec sp = cst(m.species)[k];
+                const double ybar = yk > 0.0 ? cc[i] / yk + rc * sp.inv_w * cm : 0.0;
+                const NewtonSpecies ns = cst(m.newton)[k];
                 const double h_lo = enthalpy_poly(ns.lo, cs.T, cs.invT);
                 const double h_hi = enthalpy_poly(ns.hi, cs.T, cs.invT);
-                tbar -= gam[i] * (cs.T <= m.species[k].t_mid ? h_lo : h_hi) * cs.invT;
+                tbar -= gam[i] * (cs.T <= sp.t_mid ? h_lo : h_hi) * cs.invT;
                 if (valid) Ybar[size_t(k) * ld + cell] = ybar;
             }
         }

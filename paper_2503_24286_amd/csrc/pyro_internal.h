@@ -94,6 +94,23 @@ struct NewtonSpecies {
 static_assert(sizeof(NewtonSpecies) == 128, "NewtonSpecies must be 128 bytes");
 
 // Device-side view of a mechanism, passed to kernels by value.
+// Device-side view of a read-only table as constant-address-space memory:
+// the tables never change while a kernel runs, and saying so lets the
+// compiler read wave-uniform entries with scalar loads even inside loops that
+// also store (which it cannot otherwise prove do not overwrite them).
+// (the host pass only parses device code and sees a plain pointer)
+#if defined(__HIP_DEVICE_COMPILE__)
+template <typename T>
+using cptr = const __attribute__((address_space(4))) T*;
+#else
+template <typename T>
+using cptr = const T*;
+#endif
+template <typename T>
+__device__ inline cptr<T> cst(const T* p) {
+    return (cptr<T>)(p);
+}
+
 // The tables of one work schedule (see the loader): chunks of waves x rpw
 // reaction slots, species owned per wave, gathering lists.
 struct DevSched {
