@@ -139,16 +139,20 @@ PYRO_API int pyro_production_rates(const pyro_mech* mech, int64_t n, int64_t ld,
  *   params_bar             device array of 3*n_params doubles, overwritten
  *                          with dL/d(ln A, b, Ea) in the row order of params
  *                          (Ea per J/mol); deterministic (fixed-order sums)
+ *   wdot[S*ld]             optional output (NULL to skip): the net production
+ *                          rates of the same state, from the forward
+ *                          recomputation the reverse sweep performs anyway
+ *                          (equal to pyro_production_rates up to rounding order)
  *   params                 Arrhenius triples to differentiate at, or NULL
  * The call allocates a temporary workspace on the stream (stream-ordered).
  * FP64 only.  PYRO_E_UNSUPPORTED for mechanisms whose tables exceed the
- * kernel's LDS tile or more than 512 reactions.
+ * kernel's LDS tile or with more than 16 species per wavefront.
  */
 PYRO_API int pyro_production_rates_vjp(const pyro_mech* mech, int64_t n, int64_t ld,
                                        const double* rho, const double* T,
                                        const double* Y, const double* wbar,
                                        double* Ybar, double* Tbar, double* params_bar,
-                                       const double* params, void* stream);
+                                       double* wdot, const double* params, void* stream);
 
 /*
  * Temperature from the mass-specific internal energy by Newton iteration

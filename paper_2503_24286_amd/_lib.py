@@ -50,7 +50,7 @@ SIGNATURES = {
     "pyro_mech_molecular_weights": (_I, [_P, _P]),
     "pyro_mech_arrhenius": (_I, [_P, _P]),
     "pyro_production_rates": (_I, [_P, _I64, _I64, _I, _P, _P, _P, _P, _P, _P]),
-    "pyro_production_rates_vjp": (_I, [_P, _I64, _I64, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
+    "pyro_production_rates_vjp": (_I, [_P, _I64, _I64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "pyro_temperature": (_I, [_P, _I64, _I64, _P, _P, _P, _D, _P, _P, _I, _D, _P]),
     "pyro_density": (_I, [_P, _I64, _I64, _P, _P, _P, _P, _P]),
     "pyro_pressure": (_I, [_P, _I64, _I64, _P, _P, _P, _P, _P]),

@@ -169,9 +169,11 @@ def internal_energy(mech, T, Y, out=None):
 
 
 def production_rates_vjp(mech, rho, T, Y, wbar, params=None, Ybar=None, Tbar=None,
-                         params_bar=None):
+                         params_bar=None, wdot=None):
     """Gradients of L = sum wbar * omega (fixed rho): returns (Ybar, Tbar,
-    params_bar) with params_bar of shape (n_params, 3) = dL/d(ln A, b, Ea)."""
+    params_bar) with params_bar of shape (n_params, 3) = dL/d(ln A, b, Ea).
+    ``wdot``, an (S, n) view with the row stride of Y, also receives omega
+    from the same pass."""
     S = mech.n_species
     n = Y.shape[1]
     ld = _species_major(Y, S, torch.float64, "Y")
@@ -191,9 +193,11 @@ def production_rates_vjp(mech, rho, T, Y, wbar, params=None, Ybar=None, Tbar=Non
         if params.dtype != torch.float64 or params.numel() != 3 * mech.n_params:
             raise ValueError("params must hold 3*n_params float64 values")
         params = params.contiguous()
+    if wdot is not None and _species_major(wdot, S, torch.float64, "wdot") != ld:
+        raise ValueError("wdot must have the row stride of Y")
     check(lib().pyro_production_rates_vjp(
         mech.handle, n, ld, _ptr(rho), _ptr(T), _ptr(Y), _ptr(wbar), _ptr(Ybar), _ptr(Tbar),
-        _ptr(params_bar), _ptr(params), _stream(Y.device)))
+        _ptr(params_bar), _ptr(wdot), _ptr(params), _stream(Y.device)))
     return Ybar, Tbar, params_bar
 
 

@@ -124,8 +124,8 @@ int pyro_production_rates(const pyro_mech* m, int64_t n, int64_t ld, int dtype, 
 
 int pyro_production_rates_vjp(const pyro_mech* m, int64_t n, int64_t ld, const double* rho,
                               const double* T, const double* Y, const double* wbar, double* Ybar,
-                              double* Tbar, double* params_bar, const double* params,
-                              void* stream) {
+                              double* Tbar, double* params_bar, double* wdot,
+                              const double* params, void* stream) {
     clear_error();
     if (int rc = check_sizes(n, ld)) return rc;
     if (int rc = check_mech(m)) return rc;
@@ -141,7 +141,7 @@ int pyro_production_rates_vjp(const pyro_mech* m, int64_t n, int64_t ld, const d
     }
     if (int rc = check_ptrs({rho, T, Y, wbar, Ybar, Tbar}, "rho, T, Y, wbar, Ybar and Tbar")) return rc;
     return launched(launch_production_rates_vjp(m, n, ld, rho, T, Y, wbar, Ybar, Tbar, params_bar,
-                                                params, s),
+                                                wdot, params, s),
                     "VJP kernel launch");
 }
 

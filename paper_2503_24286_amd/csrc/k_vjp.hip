@@ -31,8 +31,7 @@ namespace pyro {
 namespace {
 
 constexpr int kVRow = kTile * 24;                   // C[64], G[64], wbar[64]
-constexpr int kPlane = kChunk * kTile * 8;          // a or b: [slot][cell]
-constexpr int kBuf = 2 * kPlane;                    // one chunk buffer: a and b planes
+constexpr int kPlane = kChunk * kTile * 8;          // a, b or q: [slot][cell]
 static_assert(kVjpWaves == kChunk, "one reaction per wavefront fills a chunk's slots");
 
 struct CGW {
@@ -79,7 +78,7 @@ struct CellState {
 };
 
 struct RevOut {
-    double a, b, xbar, xbar0, Mbar, Tbar;
+    double a, b, q, xbar, xbar0, Mbar, Tbar;
 };
 
 // Forward recomputation and reverse sweep of one reaction for one cell.
@@ -169,6 +168,7 @@ __device__ inline RevOut reaction_vjp(const DevMech& m, const RxnRec& r,
     const double phi = r.cls == kThirdBody ? M : 1.0;
     const double Dbar = qbar * phi;
     RevOut o;
+    o.q = phi * D;
     o.a = Dbar * Rf;
     o.b = Dbar * Rr;
     const double xeff = Dbar * D;
@@ -213,20 +213,31 @@ __device__ inline double wave_sum(double v) {
     return v;
 }
 
-template <int MAXOWN, int MAXPD>
+// LDS of the reverse sweep: species rows, then a region holding the two
+// chunk buffers during the chunk loop and, after it, Mbar [n_pd][64] and the
+// per-wave temperature partials [kVjpWaves][64], then the parameter sums
+__host__ __device__ inline size_t vjp_region_bytes(int n_pd) {
+    const size_t chunks = 2 * 3 * size_t(kPlane);
+    const size_t after = (size_t(n_pd) + kVjpWaves) * kTile * 8;
+    return chunks > after ? chunks : after;
+}
+
+// WITH_W: also the net production rates, gathered from a third plane (q)
+template <int MAXOWN, int MAXPD, bool WITH_W>
 __global__ __launch_bounds__(kVjpWaves * 64) void vjp_kernel(
     DevMech m, int64_t n, int64_t ld, const double* __restrict__ rho,
     const double* __restrict__ T, const double* __restrict__ Y,
     const double* __restrict__ wbar, double* __restrict__ Ybar, double* __restrict__ Tbar,
-    double* __restrict__ partial, const double* __restrict__ params) {
-    // LDS: species rows, two chunk buffers, Mbar [n_pd][64], parameter sums
+    double* __restrict__ wdot, double* __restrict__ partial, const double* __restrict__ params) {
+    constexpr int kBuf = (WITH_W ? 3 : 2) * kPlane;   // one chunk buffer: a, b (, q) planes
     extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
     const DevSched& sc = m.vjp;
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     unsigned char* bufs = lds + size_t(m.S) * kVRow;
-    double* mbar = reinterpret_cast<double*>(bufs + 2 * kBuf);                 // [n_pd][64]
-    double* pacc = mbar + size_t(m.n_pd) * kTile;                             // [R + n_fo][3]
+    double* mbar = reinterpret_cast<double*>(bufs);                           // after the loop
+    double* tb = mbar + size_t(m.n_pd) * kTile;                               // after the loop
+    double* pacc = reinterpret_cast<double*>(bufs + vjp_region_bytes(m.n_pd)); // [R + n_fo][3]
     const int n_rows = m.R + m.n_fo;
     for (int i = threadIdx.x; i < 3 * n_rows; i += kVjpWaves * 64) pacc[i] = 0.0;
 
@@ -290,21 +301,25 @@ __global__ __launch_bounds__(kVjpWaves * 64) void vjp_kernel(
             }
         }
 
-        double cc[MAXOWN], gam[MAXOWN];
+        double cc[MAXOWN], gam[MAXOWN], ws[MAXOWN];
 #pragma unroll
-        for (int i = 0; i < MAXOWN; ++i) cc[i] = gam[i] = 0.0;
+        for (int i = 0; i < MAXOWN; ++i) cc[i] = gam[i] = ws[i] = 0.0;
         double tbar = 0.0;
 
         for (int ch = 0; ch < sc.n_chunks; ++ch) {
             unsigned char* plane_a = bufs + (ch & 1) * kBuf;
             unsigned char* plane_b = plane_a + kPlane;
+            unsigned char* plane_q = plane_b + kPlane;
             const RxnRec r = cst(sc.rxn)[size_t(ch) * kVjpWaves + w];
             if (r.cls != kNoReaction) {
                 const double M = r.cls >= kThirdBody ? pop_front(Mr) : 1.0;
                 const RevOut o = reaction_vjp(m, r, params, lds, lane, M, cs);
                 *reinterpret_cast<double*>(plane_a + r.qoff + lane * 8) = o.a;
                 *reinterpret_cast<double*>(plane_b + r.qoff + lane * 8) = o.b;
-                if (r.cls >= kThirdBody) mbar[size_t(r.pd) * kTile + lane] = o.Mbar;
+                if (WITH_W) *reinterpret_cast<double*>(plane_q + r.qoff + lane * 8) = o.q;
+                // the consumed [M] slot now holds this reaction's Mbar: after
+                // the loop the queue's tail holds them in chunk order
+                if (r.cls >= kThirdBody) Mr[MAXPD - 1] = o.Mbar;
                 tbar += o.Tbar;
                 // cell sums of xbar (1, ln T, -1/(R T)) into this reaction's rows
                 const double s0 = wave_sum(o.xbar);
@@ -341,6 +356,7 @@ __global__ __launch_bounds__(kVjpWaves * 64) void vjp_kernel(
                 if (i < nown) {
                     // two entries per step, their loads issued together
                     double sc0 = cc[i], sg0 = gam[i], sc1 = 0.0, sg1 = 0.0;
+                    double sw0 = ws[i], sw1 = 0.0;
                     int e = bound[i];
                     for (; e + 1 < bound[i + 1]; e += 2) {
                         const uint32_t g0 = gent[e], g1 = gent[e + 1];
@@ -355,6 +371,12 @@ __global__ __launch_bounds__(kVjpWaves * 64) void vjp_kernel(
                         sg0 = fma(f0 - r0, b0, sg0);
                         sc1 = fma(f1, a1, fma(-r1, b1, sc1));
                         sg1 = fma(f1 - r1, b1, sg1);
+                        if (WITH_W) {
+                            const double q0 = *reinterpret_cast<const double*>(plane_q + o0);
+                            const double q1 = *reinterpret_cast<const double*>(plane_q + o1);
+                            sw0 = fma(r0 - f0, q0, sw0);
+                            sw1 = fma(r1 - f1, q1, sw1);
+                        }
                     }
                     if (e < bound[i + 1]) {
                         const uint32_t g = gent[e];
@@ -364,15 +386,27 @@ __global__ __launch_bounds__(kVjpWaves * 64) void vjp_kernel(
                         const double nf = double((g >> 16) & 0xffu), nr = double(g >> 24);
                         sc0 = fma(nf, av, fma(-nr, bv, sc0));
                         sg0 = fma(nf - nr, bv, sg0);
+                        if (WITH_W)
+                            sw0 = fma(nr - nf, *reinterpret_cast<const double*>(plane_q + off), sw0);
                     }
                     cc[i] = sc0 + sc1;
                     gam[i] = sg0 + sg1;
+                    ws[i] = sw0 + sw1;
                 }
             }
         }
 
-        // ---- species results (every Mbar was written before the last
-        // chunk's barrier)
+        // ---- Mbar of this wave's third-body reactions into LDS, once every
+        // wave is done with the chunk buffers
+        __syncthreads();
+        {
+            const cptr<int32_t> pl = cst(sc.pd_list) + w * kMaxPd;
+#pragma unroll
+            for (int p = 0; p < MAXPD; ++p)
+                if (p >= MAXPD - npdw) mbar[size_t(pl[p - (MAXPD - npdw)]) * kTile + lane] = Mr[p];
+        }
+        __syncthreads();
+        // ---- species results
 #pragma unroll
         for (int i = 0; i < MAXOWN; ++i) {
             if (i < nown) {
@@ -398,12 +432,13 @@ __global__ __launch_bounds__(kVjpWaves * 64) void vjp_kernel(
                 const double h_lo = enthalpy_poly(ns.lo, cs.T, cs.invT);
                 const double h_hi = enthalpy_poly(ns.hi, cs.T, cs.invT);
                 tbar -= gam[i] * (cs.T <= sp.t_mid ? h_lo : h_hi) * cs.invT;
-                if (valid) Ybar[size_t(k) * ld + cell] = ybar;
+                if (valid) {
+                    Ybar[size_t(k) * ld + cell] = ybar;
+                    if (WITH_W) wdot[size_t(k) * ld + cell] = ws[i];
+                }
             }
         }
-        // ---- temperature: per-wave partials summed in wave order, staged in
-        // the chunk buffer the last chunk did not use
-        double* tb = reinterpret_cast<double*>(bufs + (sc.n_chunks & 1) * kBuf);
+        // ---- temperature: per-wave partials summed in wave order
         tb[w * kTile + lane] = tbar;
         __syncthreads();
         if (w == 0) {
@@ -428,39 +463,48 @@ __global__ void vjp_reduce_kernel(int rows3, int blocks, const double* __restric
     pbar[idx] = s;
 }
 
-template <int MAXOWN, int MAXPD>
+template <int MAXOWN, int MAXPD, bool WITH_W>
 hipError_t set_lds_vjp(int bytes) {
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(&vjp_kernel<MAXOWN, MAXPD>),
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&vjp_kernel<MAXOWN, MAXPD, WITH_W>),
                                hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
+struct VjpArgs {
+    int blocks;
+    int64_t n, ld;
+    const double *rho, *T, *Y, *wbar;
+    double *Ybar, *Tbar, *wdot, *partial;
+    const double* params;
+};
+
 template <int MAXOWN, int MAXPD>
-hipError_t launch_vjp(const pyro_mech* m, int blocks, int64_t n, int64_t ld, const double* rho,
-                      const double* T, const double* Y, const double* wbar, double* Ybar,
-                      double* Tbar, double* partial, const double* params, hipStream_t stream) {
-    hipLaunchKernelGGL((vjp_kernel<MAXOWN, MAXPD>), dim3(unsigned(blocks)), dim3(kVjpWaves * 64),
-                       vjp_lds_bytes(m), stream, m->dev, n, ld, rho, T, Y, wbar, Ybar, Tbar,
-                       partial, params);
+hipError_t launch_vjp(const pyro_mech* m, const VjpArgs& a, hipStream_t stream) {
+    const size_t lds = vjp_lds_bytes(m);
+    if (a.wdot)
+        hipLaunchKernelGGL((vjp_kernel<MAXOWN, MAXPD, true>), dim3(unsigned(a.blocks)),
+                           dim3(kVjpWaves * 64), lds, stream, m->dev, a.n, a.ld, a.rho, a.T, a.Y,
+                           a.wbar, a.Ybar, a.Tbar, a.wdot, a.partial, a.params);
+    else
+        hipLaunchKernelGGL((vjp_kernel<MAXOWN, MAXPD, false>), dim3(unsigned(a.blocks)),
+                           dim3(kVjpWaves * 64), lds, stream, m->dev, a.n, a.ld, a.rho, a.T, a.Y,
+                           a.wbar, a.Ybar, a.Tbar, a.wdot, a.partial, a.params);
     return hipGetLastError();
 }
 
 template <int MAXOWN>
-hipError_t launch_vjp_own(const pyro_mech* m, int blocks, int64_t n, int64_t ld,
-                          const double* rho, const double* T, const double* Y, const double* wbar,
-                          double* Ybar, double* Tbar, double* partial, const double* params,
-                          hipStream_t stream) {
-    if (m->vjp_max_pdw <= 4)
-        return launch_vjp<MAXOWN, 4>(m, blocks, n, ld, rho, T, Y, wbar, Ybar, Tbar, partial, params, stream);
-    if (m->vjp_max_pdw <= 8)
-        return launch_vjp<MAXOWN, 8>(m, blocks, n, ld, rho, T, Y, wbar, Ybar, Tbar, partial, params, stream);
-    return launch_vjp<MAXOWN, 16>(m, blocks, n, ld, rho, T, Y, wbar, Ybar, Tbar, partial, params, stream);
+hipError_t launch_vjp_own(const pyro_mech* m, const VjpArgs& a, hipStream_t stream) {
+    if (m->vjp_max_pdw <= 4) return launch_vjp<MAXOWN, 4>(m, a, stream);
+    if (m->vjp_max_pdw <= 8) return launch_vjp<MAXOWN, 8>(m, a, stream);
+    return launch_vjp<MAXOWN, 16>(m, a, stream);
 }
 
 template <int MAXOWN>
 hipError_t set_lds_own(int bytes) {
     hipError_t e = hipSuccess;
-    const hipError_t all[] = {set_lds_vjp<MAXOWN, 4>(bytes), set_lds_vjp<MAXOWN, 8>(bytes),
-                              set_lds_vjp<MAXOWN, 16>(bytes)};
+    const hipError_t all[] = {
+        set_lds_vjp<MAXOWN, 4, false>(bytes), set_lds_vjp<MAXOWN, 8, false>(bytes),
+        set_lds_vjp<MAXOWN, 16, false>(bytes), set_lds_vjp<MAXOWN, 4, true>(bytes),
+        set_lds_vjp<MAXOWN, 8, true>(bytes), set_lds_vjp<MAXOWN, 16, true>(bytes)};
     for (hipError_t x : all)
         if (x != hipSuccess) e = x;
     return e;
@@ -469,7 +513,7 @@ hipError_t set_lds_own(int bytes) {
 }  // namespace
 
 size_t vjp_lds_bytes(const pyro_mech* m) {
-    return size_t(m->S) * kVRow + 2 * kBuf + size_t(m->n_tb + m->n_fo) * kTile * 8 +
+    return size_t(m->S) * kVRow + vjp_region_bytes(m->n_tb + m->n_fo) +
            size_t(m->R + m->n_fo) * 3 * 8;
 }
 
@@ -487,7 +531,7 @@ hipError_t prepare_vjp(const pyro_mech* m) {
 hipError_t launch_production_rates_vjp(const pyro_mech* m, int64_t n, int64_t ld,
                                        const double* rho, const double* T, const double* Y,
                                        const double* wbar, double* Ybar, double* Tbar,
-                                       double* params_bar, const double* params,
+                                       double* params_bar, double* wdot, const double* params,
                                        hipStream_t stream) {
     const int64_t n_tiles = (n + kTile - 1) / kTile;
     const int blocks = int(std::min<int64_t>(n_tiles, int64_t(m->n_cu)));
@@ -496,17 +540,17 @@ hipError_t launch_production_rates_vjp(const pyro_mech* m, int64_t n, int64_t ld
     void* partial = nullptr;
     hipError_t e = hipMallocAsync(&partial, pbytes > 0 ? pbytes : 8, stream);
     if (e != hipSuccess) return e;
-    const double* pp = params ? params : m->dev.params;
-    double* part = static_cast<double*>(partial);
+    const VjpArgs a{blocks, n, ld, rho, T, Y, wbar, Ybar, Tbar, wdot,
+                    static_cast<double*>(partial), params ? params : m->dev.params};
     if (m->vjp_max_own <= 4)
-        e = launch_vjp_own<4>(m, blocks, n, ld, rho, T, Y, wbar, Ybar, Tbar, part, pp, stream);
+        e = launch_vjp_own<4>(m, a, stream);
     else if (m->vjp_max_own <= 8)
-        e = launch_vjp_own<8>(m, blocks, n, ld, rho, T, Y, wbar, Ybar, Tbar, part, pp, stream);
+        e = launch_vjp_own<8>(m, a, stream);
     else
-        e = launch_vjp_own<16>(m, blocks, n, ld, rho, T, Y, wbar, Ybar, Tbar, part, pp, stream);
+        e = launch_vjp_own<16>(m, a, stream);
     if (e == hipSuccess && rows3 > 0) {
         hipLaunchKernelGGL(vjp_reduce_kernel, dim3((rows3 + 255) / 256), dim3(256), 0, stream,
-                           rows3, blocks, part, params_bar);
+                           rows3, blocks, a.partial, params_bar);
         e = hipGetLastError();
     }
     const hipError_t ef = hipFreeAsync(partial, stream);

@@ -532,6 +532,12 @@ int load_mechanism(const char* path, pyro_mech** out) {
     std::vector<int32_t> n_pdw, vn_pdw, own_tab, n_own, vown_tab, vn_own;
     wave_tables(fw, f.eff, pd_row, S, effw, n_pdw, own_tab, n_own);
     wave_tables(bw, f.eff, pd_row, S, veffw, vn_pdw, vown_tab, vn_own);
+    // the reverse sweep's third-body rows per wave, in the order its chunks
+    // meet them (one reaction per wave per chunk)
+    std::vector<int32_t> vpd_list(size_t(kVjpWaves) * kMaxPd, -1);
+    for (int w = 0; w < kVjpWaves; ++w)
+        for (size_t i = 0; i < bw.pd_of_wave[w].size(); ++i)
+            vpd_list[w * kMaxPd + i] = pd_row[bw.pd_of_wave[w][i]];
     std::vector<double> params = m->params;
     if (params.empty()) params.push_back(0.0);
 
@@ -559,6 +565,7 @@ int load_mechanism(const char* path, pyro_mech** out) {
         {vn_pdw.data(), vn_pdw.size() * sizeof(int32_t), 0},
         {vown_tab.data(), vown_tab.size() * sizeof(int32_t), 0},
         {vn_own.data(), vn_own.size() * sizeof(int32_t), 0},
+        {vpd_list.data(), vpd_list.size() * sizeof(int32_t), 0},
     };
     size_t total = 0;
     for (auto& p : parts) {
@@ -623,6 +630,7 @@ int load_mechanism(const char* path, pyro_mech** out) {
     v.n_pdw = reinterpret_cast<const int32_t*>(base + parts[18].off);
     v.own = reinterpret_cast<const int32_t*>(base + parts[19].off);
     v.n_own = reinterpret_cast<const int32_t*>(base + parts[20].off);
+    v.pd_list = reinterpret_cast<const int32_t*>(base + parts[21].off);
     err = prepare_production_rates(m);
     if (err == hipSuccess) err = prepare_vjp(m);
     if (err != hipSuccess) {

@@ -123,6 +123,7 @@ struct DevSched {
     const int32_t* n_own;                // [waves]
     const int32_t* gptr;                 // [n_chunks][waves][kMaxOwn + 1]
     const uint32_t* gent;                // reverse sweep: slot offset | nu' << 16 | nu'' << 24
+    const int32_t* pd_list;              // [waves][kMaxPd] third-body rows in chunk order
 };
 
 struct DevMech {
@@ -207,8 +208,8 @@ hipError_t prepare_production_rates(const pyro_mech* m);
 hipError_t launch_production_rates_vjp(const pyro_mech* m, int64_t n, int64_t ld,
                                        const double* rho, const double* T, const double* Y,
                                        const double* wbar, double* Ybar, double* Tbar,
-                                       double* params_bar, const double* params,
-                                       hipStream_t stream);
+                                       double* params_bar, double* wdot,
+                                       const double* params, hipStream_t stream);
 size_t vjp_lds_bytes(const pyro_mech* m);
 hipError_t prepare_vjp(const pyro_mech* m);
 

@@ -262,3 +262,32 @@ def test_vjp_full_size(lib_mechs):
     sP_scale = np.abs(pb.cpu().numpy()) + np.abs(p1.cpu().numpy()) + np.abs(p2.cpu().numpy())
     diff = np.abs((p1 + p2 - pb).cpu().numpy())
     assert np.all(diff <= 1e-9 * sP_scale + 1e-300)
+
+
+@pytest.mark.parametrize("cfg,n", [(0, 200), (1, 1000 + 29)])
+def test_vjp_also_returns_the_production_rates(lib_mechs, cfg, n):
+    """The optional omega output of the reverse sweep passes the forward
+    kernel's parity bar against the oracle, and requesting it leaves every
+    gradient bitwise unchanged."""
+    from parity import assert_wdot_parity
+    torch, pyro, gms = lib_mechs
+    m = mechs.load_config(cfg)
+    T, p, Y, rho = states(2 if cfg == 1 else 0, n, m.S, first=777)
+    wbar = draw_cotangent(2, n, m.S)
+    ld = n + 3
+    announce(f"vjp with omega cfg{cfg} n={n}")
+    r, t, wb = to_dev(torch, rho, T, wbar)
+    y = torch.zeros((m.S, ld), dtype=torch.float64, device="cuda")[:, :n]
+    y.copy_(torch.from_numpy(Y))
+    wbl = torch.zeros((m.S, ld), dtype=torch.float64, device="cuda")[:, :n]
+    wbl.copy_(wb)
+    w = torch.full((m.S, ld), 7.0, dtype=torch.float64, device="cuda")[:, :n]
+    Yb1, Tb1, pb1 = pyro.production_rates_vjp(gms[cfg], r, t, y, wbl, wdot=w)
+    Yb0, Tb0, pb0 = pyro.production_rates_vjp(gms[cfg], r, t, y, wbl)
+    torch.cuda.synchronize()
+    assert_wdot_parity(m, rho, T, Y, w.cpu().numpy())
+    for a, b in ((Yb1, Yb0), (Tb1, Tb0), (pb1, pb0)):
+        assert torch.equal(a, b)
+    # padding columns of the strided output are untouched
+    full = w.as_strided((m.S, ld), (ld, 1)).cpu().numpy()
+    assert np.all(full[:, n:] == 7.0)
