@@ -5,17 +5,20 @@
 // One wavefront owns 32 cells.  Each layer is computed transposed,
 // out^T [N x 32 cells] = W^T [N x K] in^T [K x 32 cells], with
 // v_mfma_f32_32x32x16_bf16: the A operand (weights) is a pre-packed 16-byte
-// fragment per lane read from global memory (L1/L2-resident: every wave
-// reads the same 160 K weights), the B operand is the previous layer's
-// output.  Lane l holds, for cell l%32, the outputs 8(i/4) + 4(l/32) + i%4
+// fragment per lane, the B operand is the previous layer's output.  The
+// workgroup's wavefronts share the weights: each two-K-step slice of a layer
+// is copied once into LDS (double-buffered, the next slice's global loads in
+// flight while the current one multiplies) and read from there by every
+// wavefront.  Lane l holds, for cell l%32, the outputs 8(i/4) + 4(l/32) + i%4
 // of each 32-row block (register i).  Reading registers 8t..8t+7 of block
 // ob as the B operand of K-step 2 ob + t therefore sums over the inputs
 // 32 ob + 16 t + 8(j/4) + 4(l/32) + j%4 (j = 0..7) of the next layer; the
 // packed weights of layers 2..4 follow that order, so no data moves
 // between layers.
 //
-// Weight fragments: [ob][ks][lane][8] per layer, ob = output block of 32,
-// ks = K-step of 16; biases [ob][l/32][16] in the register order above.
+// Weight fragments: [ks][ob][lane][8] per layer, ks = K-step of 16, ob =
+// output block of 32 (a slice of K-steps is contiguous); biases
+// [ob][l/32][16] in the register order above.
 #include "pyro_internal.h"
 #include "surrogate_internal.h"
 
@@ -27,12 +30,17 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kCells = 32;                 // cells per wavefront
-constexpr int kWavesPerBlock = 4;
 constexpr int kFeatRow = kFeatPad + 8;     // padded LDS feature row (bf16)
-constexpr int kFeatBytes = kWavesPerBlock * kCells * kFeatRow * 2;
+constexpr int kSliceKs = 2;                // K-steps per staged weight slice
 
-__host__ __device__ constexpr size_t fused_lds_bytes(int members) {
-    return size_t(kFeatBytes) + size_t(kWavesPerBlock) * members * 32 * 64 * 4;
+// wavefronts per workgroup: four share the weights; five or more members'
+// outputs would not fit in LDS beside them, so four members use two
+__host__ __device__ constexpr int waves_per_block(int members) { return members <= 3 ? 4 : 2; }
+
+// LDS: feature rows, member outputs, two weight slices of the widest layer
+__host__ __device__ constexpr size_t fused_lds_bytes(int H, int members) {
+    return size_t(waves_per_block(members)) * (kCells * kFeatRow * 2 + members * 32 * 64 * 4) +
+           2 * size_t(kSliceKs) * (H / 32) * 64 * 16;
 }
 
 __device__ inline uint16_t f2bf(float f) {
@@ -90,7 +98,7 @@ __global__ void pack_kernel(int H, int members, int64_t w_total, int64_t b_total
         const int64_t q = p - P.w_off[l];
         const int j = int(q & 7), lane = int((q >> 3) & 63);
         const int64_t frag = q >> 9;
-        const int ks = int(frag % P.ks[l]), ob = int(frag / P.ks[l]);
+        const int ob = int(frag % P.nb[l]), ks = int(frag / P.nb[l]);
         // natural weights of layer l: [K][N] row-major after the previous layers
         int64_t nat = 0;
         for (int i = 0; i < l; ++i) nat += int64_t(K[i]) * N[i];
@@ -124,9 +132,17 @@ struct FusedArgs {
     float* zout;           // raw mode: [members][n][64]
 };
 
-template <int NB, int KS>
-__device__ inline void layer(f32x16 (&acc)[NB], const bf16x8 (&in)[KS], const uint16_t* __restrict__ wp,
-                             const float* __restrict__ bp, int lane) {
+// One layer for the wavefront's 32 cells: acc = bias + W^T in, with the
+// weight slices staged through LDS by the whole workgroup (NT threads).
+// Every call ends with a barrier, so the next call may refill both buffers.
+template <int NB, int KS, int NT>
+__device__ inline void layer(f32x16 (&acc)[NB], const bf16x8 (&in)[KS],
+                             const uint16_t* __restrict__ wp, const float* __restrict__ bp,
+                             u32x4* wbuf, int lane, int tid) {
+    constexpr int kUnits = kSliceKs * NB * 64;          // 16-byte fragments per slice
+    constexpr int kPer = (kUnits + NT - 1) / NT;        // per thread
+    constexpr int kSlices = KS / kSliceKs;
+    static_assert(KS % kSliceKs == 0, "K-steps come in whole slices");
     const int h = lane >> 5;
 #pragma unroll
     for (int ob = 0; ob < NB; ++ob) {
@@ -140,24 +156,34 @@ __device__ inline void layer(f32x16 (&acc)[NB], const bf16x8 (&in)[KS], const ui
             acc[ob][4 * q + 3] = v.w;
         }
     }
-    const u32x4* frag = reinterpret_cast<const u32x4*>(wp) + lane;
-    // fragments of K-step ks + 1 are in flight while step ks multiplies
-    u32x4 cur[NB], nxt[NB];
+    const u32x4* src = reinterpret_cast<const u32x4*>(wp);
 #pragma unroll
-    for (int ob = 0; ob < NB; ++ob) cur[ob] = frag[(ob * KS) * 64];
-    // fully unrolled: the operand array is indexed by compile-time constants
+    for (int j = 0; j < kPer; ++j)
+        if (tid + j * NT < kUnits) wbuf[tid + j * NT] = src[tid + j * NT];
+    __syncthreads();
 #pragma unroll
-    for (int ks = 0; ks < KS; ++ks) {
-        if (ks + 1 < KS) {
+    for (int sl = 0; sl < kSlices; ++sl) {
+        const u32x4* cur = wbuf + (sl & 1) * kUnits;
+        u32x4* nxt = wbuf + ((sl + 1) & 1) * kUnits;
+        u32x4 pre[kPer];
+        if (sl + 1 < kSlices) {
 #pragma unroll
-            for (int ob = 0; ob < NB; ++ob) nxt[ob] = frag[(ob * KS + ks + 1) * 64];
+            for (int j = 0; j < kPer; ++j)
+                if (tid + j * NT < kUnits) pre[j] = src[(sl + 1) * kUnits + tid + j * NT];
         }
 #pragma unroll
-        for (int ob = 0; ob < NB; ++ob)
-            acc[ob] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                __builtin_bit_cast(bf16x8, cur[ob]), in[ks], acc[ob], 0, 0, 0);
+        for (int kk = 0; kk < kSliceKs; ++kk)
 #pragma unroll
-        for (int ob = 0; ob < NB; ++ob) cur[ob] = nxt[ob];
+            for (int ob = 0; ob < NB; ++ob)
+                acc[ob] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                    __builtin_bit_cast(bf16x8, cur[(kk * NB + ob) * 64 + lane]),
+                    in[sl * kSliceKs + kk], acc[ob], 0, 0, 0);
+        if (sl + 1 < kSlices) {
+#pragma unroll
+            for (int j = 0; j < kPer; ++j)
+                if (tid + j * NT < kUnits) nxt[tid + j * NT] = pre[j];
+        }
+        __syncthreads();
     }
 }
 
@@ -180,19 +206,25 @@ __device__ inline void activate(const f32x16 (&acc)[NB], bf16x8 (&out)[2 * NB]) 
 }
 
 template <int H, int E, bool RAW>
-__global__ __launch_bounds__(kWavesPerBlock * 64) void fused_kernel(
+__global__ __launch_bounds__(waves_per_block(E) * 64) void fused_kernel(
     DevMech m, int64_t n, int64_t ld, const double* __restrict__ rho,
     const double* __restrict__ T, const double* __restrict__ Y, FusedArgs a) {
     constexpr int NBH = H / 32, KSH = H / 16;
-    // LDS: feature rows [wave][cell][kFeatRow] (BF16), then the member
-    // outputs [wave][member][register][lane] (FP32, lane-contiguous)
+    constexpr int WPB = waves_per_block(E), NT = WPB * 64;
+    // LDS: feature rows [wave][cell][kFeatRow] (BF16), the member outputs
+    // [wave][member][register][lane] (FP32, lane-contiguous), then two
+    // weight slices
     extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
-    const int lane = threadIdx.x & 63;
-    const int wv = threadIdx.x >> 6;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wv = tid >> 6;
     uint16_t* feat = reinterpret_cast<uint16_t*>(lds) + wv * kCells * kFeatRow;
-    float* zl = reinterpret_cast<float*>(lds + kFeatBytes) + wv * E * 32 * 64 + lane;
-    const int64_t c0 = (int64_t(blockIdx.x) * kWavesPerBlock + wv) * kCells;
-    if (c0 >= n) return;  // whole wavefront; the kernel has no block barrier
+    unsigned char* zbase = lds + WPB * kCells * kFeatRow * 2;
+    float* zl = reinterpret_cast<float*>(zbase) + wv * E * 32 * 64 + lane;
+    u32x4* wbuf = reinterpret_cast<u32x4*>(zbase + WPB * E * 32 * 64 * 4);
+    // every wavefront takes part in the weight staging and its barriers;
+    // cells past n compute on cell n - 1 and write nothing
+    const int64_t c0 = (int64_t(blockIdx.x) * WPB + wv) * kCells;
     const int cl = lane & 31, h = lane >> 5;
     const int64_t cell = c0 + cl;
     const bool valid = cell < n;
@@ -231,14 +263,14 @@ __global__ __launch_bounds__(kWavesPerBlock * 64) void fused_kernel(
         const float* bp = a.bp + e * a.b_stride;
         f32x16 acc[NBH];
         bf16x8 act[KSH];
-        layer<NBH, 4>(acc, xb, wp + P.w_off[0], bp + P.b_off[0], lane);
+        layer<NBH, 4, NT>(acc, xb, wp + P.w_off[0], bp + P.b_off[0], wbuf, lane, tid);
         activate<NBH>(acc, act);
-        layer<NBH, KSH>(acc, act, wp + P.w_off[1], bp + P.b_off[1], lane);
+        layer<NBH, KSH, NT>(acc, act, wp + P.w_off[1], bp + P.b_off[1], wbuf, lane, tid);
         activate<NBH>(acc, act);
-        layer<NBH, KSH>(acc, act, wp + P.w_off[2], bp + P.b_off[2], lane);
+        layer<NBH, KSH, NT>(acc, act, wp + P.w_off[2], bp + P.b_off[2], wbuf, lane, tid);
         activate<NBH>(acc, act);
         f32x16 z[2];
-        layer<2, KSH>(z, act, wp + P.w_off[3], bp + P.b_off[3], lane);
+        layer<2, KSH, NT>(z, act, wp + P.w_off[3], bp + P.b_off[3], wbuf, lane, tid);
 #pragma unroll
         for (int ob = 0; ob < 2; ++ob)
 #pragma unroll
@@ -264,18 +296,26 @@ __global__ __launch_bounds__(kWavesPerBlock * 64) void fused_kernel(
         double wm[2][16];
         double mean2 = 0.0, dev2 = 0.0;
         bool finite = true;
+        // a lane's species is k0 (half 0) or k0 + 4 (half 1): both table
+        // entries come from scalar loads and the lane selects its own
+        const cptr<double> ts = cst(a.ts), tmu = cst(a.tmu), tsig = cst(a.tsig);
 #pragma unroll
         for (int ob = 0; ob < 2; ++ob)
 #pragma unroll
             for (int i = 0; i < 16; ++i) {
-                const int k = output_index(ob, h, i);
+                const int k0 = output_index(ob, 0, i);
+                const int k = k0 + 4 * h;
                 const int r = ob * 16 + i;
                 wm[ob][i] = 0.0;
+                if (k0 >= m.S) continue;
+                const bool has1 = k0 + 4 < m.S;
+                const double s = h ? (has1 ? ts[k0 + 4] : 1.0) : ts[k0];
+                const double mu = h ? (has1 ? tmu[k0 + 4] : 0.0) : tmu[k0];
+                const double sg = h ? (has1 ? tsig[k0 + 4] : 0.0) : tsig[k0];
                 if (k < m.S) {
                     float zs = 0.0f;
 #pragma unroll
                     for (int e = 0; e < E; ++e) zs += zl[(e * 32 + r) * 64];
-                    const double s = a.ts[k], mu = a.tmu[k], sg = a.tsig[k];
                     const double w = s * sinh(fma(sg, double(zs * inv_e), mu));
                     wm[ob][i] = w;
                     finite = finite && isfinite(w);
@@ -294,18 +334,18 @@ __global__ __launch_bounds__(kWavesPerBlock * 64) void fused_kernel(
         // element residual ||A w|| / || |A| |w| ||
         double r2 = 0.0, q2 = 0.0;
         for (int el = 0; el < m.E; ++el) {
-            const double* ce = m.comp + size_t(el) * m.S;
+            const cptr<double> ce = cst(m.comp) + size_t(el) * m.S;
             double r = 0.0, q = 0.0;
 #pragma unroll
             for (int ob = 0; ob < 2; ++ob)
 #pragma unroll
                 for (int i = 0; i < 16; ++i) {
-                    const int k = output_index(ob, h, i);
-                    if (k < m.S) {
-                        const double ak = ce[k];
-                        r = fma(ak, wm[ob][i], r);
-                        q = fma(fabs(ak), fabs(wm[ob][i]), q);
-                    }
+                    const int k0 = output_index(ob, 0, i);
+                    if (k0 >= m.S) continue;
+                    // wm is zero for a lane whose species is past S
+                    const double ak = h ? (k0 + 4 < m.S ? ce[k0 + 4] : 0.0) : ce[k0];
+                    r = fma(ak, wm[ob][i], r);
+                    q = fma(fabs(ak), fabs(wm[ob][i]), q);
                 }
             r += __shfl_xor(r, 32);
             q += __shfl_xor(q, 32);
@@ -331,18 +371,19 @@ template <int H, int E>
 hipError_t launch_fused_he(const pyro_mech* m, int64_t n, int64_t ld, const double* rho,
                            const double* T, const double* Y, const FusedArgs& a, bool raw,
                            hipStream_t stream) {
+    constexpr int WPB = waves_per_block(E);
     const int64_t waves = (n + kCells - 1) / kCells;
-    const dim3 grid(unsigned((waves + kWavesPerBlock - 1) / kWavesPerBlock));
-    const size_t lds = fused_lds_bytes(E);
+    const dim3 grid(unsigned((waves + WPB - 1) / WPB));
+    const size_t lds = fused_lds_bytes(H, E);
     const void* fn = raw ? reinterpret_cast<const void*>(&fused_kernel<H, E, true>)
                          : reinterpret_cast<const void*>(&fused_kernel<H, E, false>);
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
     if (e != hipSuccess) return e;
     if (raw)
-        hipLaunchKernelGGL((fused_kernel<H, E, true>), grid, dim3(kWavesPerBlock * 64), lds,
+        hipLaunchKernelGGL((fused_kernel<H, E, true>), grid, dim3(WPB * 64), lds,
                            stream, m->dev, n, ld, rho, T, Y, a);
     else
-        hipLaunchKernelGGL((fused_kernel<H, E, false>), grid, dim3(kWavesPerBlock * 64), lds,
+        hipLaunchKernelGGL((fused_kernel<H, E, false>), grid, dim3(WPB * 64), lds,
                            stream, m->dev, n, ld, rho, T, Y, a);
     return hipGetLastError();
 }
