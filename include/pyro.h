@@ -62,6 +62,18 @@ enum pyro_dtype {
     PYRO_F32 = 1              /* float cell arrays, float arithmetic         */
 };
 
+/* How the production-rate kernel forms the equilibrium constants
+ * (eq. equil_constants): both compute the same quantity. */
+enum pyro_wdot_variant {
+    /* per species G_k = exp(g0_k/RT) in LDS, 1/K_c as products of G: S
+     * exponentials per cell, 1 KB of LDS per species for a 64-cell tile */
+    PYRO_WDOT_SPECIES_EQUILIBRIUM = 0,
+    /* per reaction exp(sum_k nu_kj g0_k/RT) from coefficients combined at
+     * load time: one exponential per reversible reaction, 512 B of LDS per
+     * species; needs every reaction's species to share one NASA7 T_mid */
+    PYRO_WDOT_REACTION_EQUILIBRIUM = 1
+};
+
 typedef struct pyro_mech pyro_mech;
 
 typedef struct pyro_mech_info {
@@ -74,7 +86,7 @@ typedef struct pyro_mech_info {
     int32_t nnz_reactant;     /* nonzero nu'_kj (species, reaction) pairs     */
     int32_t nnz_product;      /* nonzero nu''_kj pairs                       */
     int32_t nnz_net;          /* nonzero nu_kj = nu''_kj - nu'_kj pairs      */
-    int32_t pad;
+    int32_t wdot_variant;     /* current enum pyro_wdot_variant              */
 } pyro_mech_info;
 
 /* Message of the last failed call on this thread ("" if none).  The string
@@ -97,6 +109,12 @@ PYRO_API const char* pyro_last_error(void);
 PYRO_API int pyro_mech_load(const char* path, pyro_mech** out);
 PYRO_API void pyro_mech_free(pyro_mech* mech);
 PYRO_API int pyro_mech_get_info(const pyro_mech* mech, pyro_mech_info* info);
+/* Selects the production-rate kernel variant (enum pyro_wdot_variant) used by
+ * pyro_production_rates and the surrogate's fallback.  The loader picks the
+ * species variant when its LDS tile fits and the reaction variant otherwise;
+ * PYRO_E_UNSUPPORTED if the requested variant cannot run this mechanism.
+ * Not thread-safe against concurrent calls on the same handle. */
+PYRO_API int pyro_mech_set_wdot_variant(pyro_mech* mech, int variant);
 /* Copies the S molar masses (kg/mol) into host memory W_out[S]. */
 PYRO_API int pyro_mech_molecular_weights(const pyro_mech* mech, double* W_out);
 /* Copies the default Arrhenius triples (ln A, b, Ea) into host memory

@@ -21,6 +21,8 @@ STATUS_NAMES = {0: "PYRO_OK", -1: "PYRO_E_ARG", -2: "PYRO_E_IO", -3: "PYRO_E_FOR
                 -4: "PYRO_E_HIP", -5: "PYRO_E_NOMEM", -6: "PYRO_E_UNSUPPORTED"}
 PYRO_F64 = 0
 PYRO_F32 = 1
+PYRO_WDOT_SPECIES_EQUILIBRIUM = 0
+PYRO_WDOT_REACTION_EQUILIBRIUM = 1
 
 
 class PyroError(RuntimeError):
@@ -34,7 +36,7 @@ class MechInfo(ctypes.Structure):
                 ("n_elements", ctypes.c_int32), ("n_third_body", ctypes.c_int32),
                 ("n_falloff", ctypes.c_int32), ("n_params", ctypes.c_int32),
                 ("nnz_reactant", ctypes.c_int32), ("nnz_product", ctypes.c_int32),
-                ("nnz_net", ctypes.c_int32), ("pad", ctypes.c_int32)]
+                ("nnz_net", ctypes.c_int32), ("wdot_variant", ctypes.c_int32)]
 
 
 _P = ctypes.c_void_p
@@ -47,6 +49,7 @@ SIGNATURES = {
     "pyro_mech_load": (_I, [ctypes.c_char_p, ctypes.POINTER(_P)]),
     "pyro_mech_free": (None, [_P]),
     "pyro_mech_get_info": (_I, [_P, ctypes.POINTER(MechInfo)]),
+    "pyro_mech_set_wdot_variant": (_I, [_P, _I]),
     "pyro_mech_molecular_weights": (_I, [_P, _P]),
     "pyro_mech_arrhenius": (_I, [_P, _P]),
     "pyro_production_rates": (_I, [_P, _I64, _I64, _I, _P, _P, _P, _P, _P, _P]),

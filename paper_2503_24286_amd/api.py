@@ -70,6 +70,17 @@ class Mechanism:
     def handle(self):
         return self._h
 
+    @property
+    def wdot_variant(self):
+        """The production-rate kernel variant (``_lib.PYRO_WDOT_*``)."""
+        info = _lib.MechInfo()
+        check(lib().pyro_mech_get_info(self._h, ctypes.byref(info)))
+        return info.wdot_variant
+
+    @wdot_variant.setter
+    def wdot_variant(self, variant):
+        check(lib().pyro_mech_set_wdot_variant(self._h, int(variant)))
+
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             lib().pyro_mech_free(self._h)

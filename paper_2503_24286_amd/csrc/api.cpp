@@ -89,7 +89,25 @@ int pyro_mech_get_info(const pyro_mech* m, pyro_mech_info* info) {
     info->nnz_reactant = m->nnz_f;
     info->nnz_product = m->nnz_r;
     info->nnz_net = m->nnz_net;
-    info->pad = 0;
+    info->wdot_variant = m->wdot_variant;
+    return PYRO_OK;
+}
+
+int pyro_mech_set_wdot_variant(pyro_mech* m, int variant) {
+    clear_error();
+    if (!m) return fail(PYRO_E_ARG, "null mechanism handle");
+    if (variant == PYRO_WDOT_SPECIES_EQUILIBRIUM) {
+        if (production_rates_lds_bytes(m, false) > 160 * 1024)
+            return fail(PYRO_E_UNSUPPORTED, "species rows of this mechanism exceed the LDS tile");
+    } else if (variant == PYRO_WDOT_REACTION_EQUILIBRIUM) {
+        if (!m->kc_ok)
+            return fail(PYRO_E_UNSUPPORTED, "reactions mix species with different NASA7 T_mid");
+        if (production_rates_lds_bytes(m, true) > 160 * 1024)
+            return fail(PYRO_E_UNSUPPORTED, "mechanism too large for the LDS tile");
+    } else {
+        return fail(PYRO_E_ARG, "unknown production-rate variant");
+    }
+    m->wdot_variant = variant;
     return PYRO_OK;
 }
 

@@ -26,12 +26,21 @@
 //
 // The equilibrium constant of every reaction thus costs products of S
 // per-species exponentials instead of one exponential per reaction.
+//
+// Reaction-equilibrium variant (RKC): g0/(R T) is linear in the NASA7
+// coefficients, so for a reaction whose species share one T_mid,
+// sum_k nu_kj g0_k/(R T) is a single polynomial with the combined
+// coefficients sum_k nu_kj a_k (prepared by the loader).  The reverse rate is
+// then k exp(dg_j) (R T/p0)^dnu prod_p C_p with one exponential per
+// reversible reaction, and LDS holds C only (half the bytes per species),
+// which lets large mechanisms fit and raises occupancy.
 #include "pyro_internal.h"
 
 namespace pyro {
 namespace {
 
 constexpr int kRow = kTile * 16;          // bytes per species row: C[64] then G[64]
+constexpr int kRowC = kTile * 8;          // RKC variant: C[64]
 constexpr int kQBuf = kChunk * kTile * 8; // bytes per chunk buffer
 
 struct CG {
@@ -75,13 +84,23 @@ __device__ inline double pop_front(double (&v)[N]) {
     return head;
 }
 
+// C of the species at byte offset ``off`` of a species row (RKC rows are
+// half as long as the C/G rows the offsets are given for)
+__device__ inline double lds_c(const unsigned char* lds, int off, int lane) {
+    return reinterpret_cast<const double*>(lds + (off >> 1))[lane];
+}
+
 // Rate of progress of one reaction for the calling lane's cell, given its
 // Arrhenius coefficient kf and, for third-body and falloff reactions, [M].
+// RKC: ``kc`` holds the reaction's combined Gibbs coefficients (low range,
+// high range, T_mid).
+template <bool RKC>
 __device__ inline double rate_of_progress(const DevMech& m, const RxnRec& r,
                                           const double* __restrict__ params,
                                           const unsigned char* lds, int lane, double kf,
                                           double M, double Tc, double lnT, double invT,
-                                          double invRT, double rtp, double irtp) {
+                                          double invRT, double rtp, double irtp,
+                                          cptr<double> kc) {
     if (r.cls >= kLindemann) {
         const double k0 = exp(log_arrhenius(params, m.R + r.fo, lnT, invRT));
         const double Pr = k0 * M / kf;
@@ -99,6 +118,34 @@ __device__ inline double rate_of_progress(const DevMech& m, const RxnRec& r,
             F = exp10(lfc / (1.0 + f1 * f1));
         }
         kf = kf * (Pr / (1.0 + Pr)) * F;
+    }
+    if constexpr (RKC) {
+        double cr = lds_c(lds, r.r[0], lane);
+        if (r.nr > 1) {
+            cr *= lds_c(lds, r.r[1], lane);
+            if (r.nr > 2) cr *= lds_c(lds, r.r[2], lane);
+        }
+        double q = kf * cr;
+        if (r.rev) {
+            double cp = lds_c(lds, r.p[0], lane);
+            if (r.np > 1) {
+                cp *= lds_c(lds, r.p[1], lane);
+                if (r.np > 2) cp *= lds_c(lds, r.p[2], lane);
+            }
+            double pw = 1.0;
+            if (r.dnu > 0)
+                for (int i = 0; i < r.dnu; ++i) pw *= rtp;
+            else
+                for (int i = 0; i < -r.dnu; ++i) pw *= irtp;
+            const double lo[7] = {kc[0], kc[1], kc[2], kc[3], kc[4], kc[5], kc[6]};
+            const double hi[7] = {kc[7], kc[8], kc[9], kc[10], kc[11], kc[12], kc[13]};
+            const double omlnT = 1.0 - lnT;
+            const double d_lo = gibbs_poly(lo, Tc, omlnT, invT);
+            const double d_hi = gibbs_poly(hi, Tc, omlnT, invT);
+            q -= kf * pw * exp(Tc <= kc[14] ? d_lo : d_hi) * cp;
+        }
+        if (r.cls == kThirdBody) q *= M;
+        return q;
     }
     // forward term k prod_r C_r
     CG a = lds_cg(lds, r.r[0], lane);
@@ -136,7 +183,7 @@ __device__ inline double rate_of_progress(const DevMech& m, const RxnRec& r,
     return q;
 }
 
-template <int MAXOWN, int MAXPD>
+template <int MAXOWN, int MAXPD, bool RKC>
 __global__ __launch_bounds__(kWaves * 64) void wdot_f64_kernel(
     DevMech m, int64_t n, int64_t ld, const double* __restrict__ rho,
     const double* __restrict__ T, const double* __restrict__ Y,
@@ -175,15 +222,19 @@ __global__ __launch_bounds__(kWaves * 64) void wdot_f64_kernel(
             const int k = own[i];
             const SpeciesRec& s = m.species[k];
             const double Ck = rc * fmax(y[i], 0.0) * s.inv_w;
-            // both ranges from scalar loads, then a per-lane select of the
-            // value (selecting the coefficient address would turn the
-            // uniform table reads into per-lane vector loads)
-            const double g_lo = gibbs_poly(s.lo, Tc, omlnT, invT);
-            const double g_hi = gibbs_poly(s.hi, Tc, omlnT, invT);
-            const double gRT = Tc <= s.t_mid ? g_lo : g_hi;
-            double* row = reinterpret_cast<double*>(lds + k * kRow) + lane;
-            row[0] = Ck;
-            row[kTile] = exp(gRT);
+            if constexpr (RKC) {
+                reinterpret_cast<double*>(lds + k * kRowC)[lane] = Ck;
+            } else {
+                // both ranges from scalar loads, then a per-lane select of the
+                // value (selecting the coefficient address would turn the
+                // uniform table reads into per-lane vector loads)
+                const double g_lo = gibbs_poly(s.lo, Tc, omlnT, invT);
+                const double g_hi = gibbs_poly(s.hi, Tc, omlnT, invT);
+                const double gRT = Tc <= s.t_mid ? g_lo : g_hi;
+                double* row = reinterpret_cast<double*>(lds + k * kRow) + lane;
+                row[0] = Ck;
+                row[kTile] = exp(gRT);
+            }
         }
     }
     __syncthreads();
@@ -195,7 +246,7 @@ __global__ __launch_bounds__(kWaves * 64) void wdot_f64_kernel(
     if (m.n_pdw[w] > 0) {
         const double* ew = m.effw + size_t(w) * m.S * kMaxPd;
         for (int k = 0; k < m.S; ++k) {
-            const double ck = reinterpret_cast<const double*>(lds + k * kRow)[lane];
+            const double ck = reinterpret_cast<const double*>(lds + k * (RKC ? kRowC : kRow))[lane];
 #pragma unroll
             for (int i = 0; i < MAXPD; ++i) Mr[i] = fma(ew[k * kMaxPd + i], ck, Mr[i]);
         }
@@ -205,7 +256,7 @@ __global__ __launch_bounds__(kWaves * 64) void wdot_f64_kernel(
     double acc[MAXOWN];
 #pragma unroll
     for (int i = 0; i < MAXOWN; ++i) acc[i] = 0.0;
-    unsigned char* qbase = lds + size_t(m.S) * kRow;
+    unsigned char* qbase = lds + size_t(m.S) * (RKC ? kRowC : kRow);
     static_assert(kRxnPerWave == 2, "the reaction phase handles reactions in pairs");
     for (int ch = 0; ch < m.n_chunks; ++ch) {
         unsigned char* qb = qbase + (ch & 1) * kQBuf;
@@ -218,12 +269,13 @@ __global__ __launch_bounds__(kWaves * 64) void wdot_f64_kernel(
         // the wave meets its third-body/falloff reactions in queue order
         const double M0 = r0.cls >= kThirdBody ? pop_front(Mr) : 1.0;
         const double M1 = r1.cls >= kThirdBody ? pop_front(Mr) : 1.0;
+        const cptr<double> kc = cst(m.rxn_kc) + (size_t(ch) * kWaves + w) * kRxnPerWave * 16;
         if (r0.cls != kNoReaction)
-            *reinterpret_cast<double*>(qb + r0.qoff + lane * 8) = rate_of_progress(
-                m, r0, params, lds, lane, kf0, M0, Tc, lnT, invT, invRT, rtp, irtp);
+            *reinterpret_cast<double*>(qb + r0.qoff + lane * 8) = rate_of_progress<RKC>(
+                m, r0, params, lds, lane, kf0, M0, Tc, lnT, invT, invRT, rtp, irtp, kc);
         if (r1.cls != kNoReaction)
-            *reinterpret_cast<double*>(qb + r1.qoff + lane * 8) = rate_of_progress(
-                m, r1, params, lds, lane, kf1, M1, Tc, lnT, invT, invRT, rtp, irtp);
+            *reinterpret_cast<double*>(qb + r1.qoff + lane * 8) = rate_of_progress<RKC>(
+                m, r1, params, lds, lane, kf1, M1, Tc, lnT, invT, invRT, rtp, irtp, kc + 16);
         __syncthreads();
         // gather: the boundaries of all owned species in one scalar load,
         // then each species' entries in pairs
@@ -261,49 +313,61 @@ __global__ __launch_bounds__(kWaves * 64) void wdot_f64_kernel(
     }
 }
 
-template <int MAXOWN, int MAXPD>
+template <int MAXOWN, int MAXPD, bool RKC>
 hipError_t launch_f64(const pyro_mech* m, int64_t n, int64_t ld, const double* rho,
                       const double* T, const double* Y, double* wdot,
                       const double* params, hipStream_t stream, const int64_t* n_dev) {
-    const size_t lds = production_rates_lds_bytes(m);
+    const size_t lds = production_rates_lds_bytes(m, RKC);
     const int64_t blocks = (n + kTile - 1) / kTile;
-    hipLaunchKernelGGL((wdot_f64_kernel<MAXOWN, MAXPD>), dim3(unsigned(blocks)),
+    hipLaunchKernelGGL((wdot_f64_kernel<MAXOWN, MAXPD, RKC>), dim3(unsigned(blocks)),
                        dim3(kWaves * 64), lds, stream, m->dev, n, ld, rho, T, Y, wdot,
                        params ? params : m->dev.params, n_dev);
     return hipGetLastError();
 }
 
-// Kernel instances: (species owned per wave, [M] slots per wave).
-template <int MAXOWN, int MAXPD>
+// Kernel instances: (species owned per wave, [M] slots per wave, variant).
+template <int MAXOWN, int MAXPD, bool RKC>
 hipError_t set_lds(int bytes) {
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(&wdot_f64_kernel<MAXOWN, MAXPD>),
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&wdot_f64_kernel<MAXOWN, MAXPD, RKC>),
                                hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
-template <int MAXPD>
+template <int MAXPD, bool RKC>
 hipError_t dispatch_own(const pyro_mech* m, int64_t n, int64_t ld, const double* r,
                         const double* t, const double* y, double* o, const double* params,
                         hipStream_t stream, const int64_t* nd) {
-    if (m->max_own <= 8) return launch_f64<8, MAXPD>(m, n, ld, r, t, y, o, params, stream, nd);
-    if (m->max_own <= 16) return launch_f64<16, MAXPD>(m, n, ld, r, t, y, o, params, stream, nd);
-    if (m->max_own <= 32) return launch_f64<32, MAXPD>(m, n, ld, r, t, y, o, params, stream, nd);
-    return launch_f64<64, MAXPD>(m, n, ld, r, t, y, o, params, stream, nd);
+    if (m->max_own <= 8) return launch_f64<8, MAXPD, RKC>(m, n, ld, r, t, y, o, params, stream, nd);
+    if (m->max_own <= 16) return launch_f64<16, MAXPD, RKC>(m, n, ld, r, t, y, o, params, stream, nd);
+    if (m->max_own <= 32) return launch_f64<32, MAXPD, RKC>(m, n, ld, r, t, y, o, params, stream, nd);
+    return launch_f64<64, MAXPD, RKC>(m, n, ld, r, t, y, o, params, stream, nd);
+}
+
+template <bool RKC>
+hipError_t set_lds_variant(int bytes) {
+    hipError_t e = hipSuccess;
+    const hipError_t all[] = {
+        set_lds<8, 8, RKC>(bytes),   set_lds<16, 8, RKC>(bytes),  set_lds<32, 8, RKC>(bytes),
+        set_lds<64, 8, RKC>(bytes),  set_lds<8, 16, RKC>(bytes),  set_lds<16, 16, RKC>(bytes),
+        set_lds<32, 16, RKC>(bytes), set_lds<64, 16, RKC>(bytes)};
+    for (hipError_t x : all)
+        if (x != hipSuccess) e = x;
+    return e;
 }
 
 }  // namespace
 
-size_t production_rates_lds_bytes(const pyro_mech* m) {
-    return size_t(m->S) * kRow + 2 * size_t(kQBuf);
+size_t production_rates_lds_bytes(const pyro_mech* m, bool reaction_equilibrium) {
+    return size_t(m->S) * (reaction_equilibrium ? kRowC : kRow) + 2 * size_t(kQBuf);
 }
 
 hipError_t prepare_production_rates(const pyro_mech* m) {
-    const int lds = int(production_rates_lds_bytes(m));
     hipError_t e = hipSuccess;
-    const hipError_t all[] = {set_lds<8, 8>(lds),  set_lds<16, 8>(lds),  set_lds<32, 8>(lds),
-                              set_lds<64, 8>(lds), set_lds<8, 16>(lds),  set_lds<16, 16>(lds),
-                              set_lds<32, 16>(lds), set_lds<64, 16>(lds)};
-    for (hipError_t x : all)
+    for (const bool rkc : {false, true}) {
+        const size_t bytes = production_rates_lds_bytes(m, rkc);
+        if (bytes > 160 * 1024 || (rkc && !m->kc_ok)) continue;
+        const hipError_t x = rkc ? set_lds_variant<true>(int(bytes)) : set_lds_variant<false>(int(bytes));
         if (x != hipSuccess) e = x;
+    }
     return e;
 }
 
@@ -316,8 +380,12 @@ hipError_t launch_production_rates(const pyro_mech* m, int64_t n, int64_t ld, in
     const double* t = static_cast<const double*>(T);
     const double* y = static_cast<const double*>(Y);
     double* o = static_cast<double*>(wdot);
-    if (m->max_pdw <= 8) return dispatch_own<8>(m, n, ld, r, t, y, o, params, stream, n_dev);
-    return dispatch_own<16>(m, n, ld, r, t, y, o, params, stream, n_dev);
+    if (m->wdot_variant == PYRO_WDOT_REACTION_EQUILIBRIUM) {
+        if (m->max_pdw <= 8) return dispatch_own<8, true>(m, n, ld, r, t, y, o, params, stream, n_dev);
+        return dispatch_own<16, true>(m, n, ld, r, t, y, o, params, stream, n_dev);
+    }
+    if (m->max_pdw <= 8) return dispatch_own<8, false>(m, n, ld, r, t, y, o, params, stream, n_dev);
+    return dispatch_own<16, false>(m, n, ld, r, t, y, o, params, stream, n_dev);
 }
 
 }  // namespace pyro

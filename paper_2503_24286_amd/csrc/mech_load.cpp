@@ -418,10 +418,20 @@ int load_mechanism(const char* path, pyro_mech** out) {
     m->params.resize(size_t(R + n_fo) * 3);
     std::copy(f.arrh.begin(), f.arrh.end(), m->params.begin());
     std::copy(f.low.begin(), f.low.end(), m->params.begin() + size_t(R) * 3);
-    if (production_rates_lds_bytes(m) > 160 * 1024) {
+    // the reaction-equilibrium variant needs one T_mid per reaction
+    m->kc_ok = true;
+    for (int j = 0; j < R && m->kc_ok; ++j) {
+        const double tm = f.trange[3 * reac[j][0] + 1];
+        for (int k : reac[j]) m->kc_ok = m->kc_ok && f.trange[3 * k + 1] == tm;
+        for (int k : prod[j]) m->kc_ok = m->kc_ok && f.trange[3 * k + 1] == tm;
+    }
+    const bool fits_species = production_rates_lds_bytes(m, false) <= 160 * 1024;
+    const bool fits_reaction = m->kc_ok && production_rates_lds_bytes(m, true) <= 160 * 1024;
+    if (!fits_species && !fits_reaction) {
         delete m;
         return fail(PYRO_E_UNSUPPORTED, "mechanism too large for the 64-cell LDS tile");
     }
+    m->wdot_variant = fits_species ? PYRO_WDOT_SPECIES_EQUILIBRIUM : PYRO_WDOT_REACTION_EQUILIBRIUM;
 
     // ---- schedules: the forward kernel's (kWaves waves, kRxnPerWave
     // reactions each per chunk) and the reverse sweep's (kVjpWaves, one each)
@@ -540,6 +550,26 @@ int load_mechanism(const char* path, pyro_mech** out) {
             vpd_list[w * kMaxPd + i] = pd_row[bw.pd_of_wave[w][i]];
     std::vector<double> params = m->params;
     if (params.empty()) params.push_back(0.0);
+    // combined Gibbs coefficients of every reversible reaction, per forward
+    // slot: sum_k nu_kj c_k for both ranges, then T_mid (g0/RT is linear in c)
+    std::vector<double> rxn_kc(recs.size() * 16, 0.0);
+    if (m->kc_ok) {
+        for (size_t slot = 0; slot < recs.size(); ++slot) {
+            const RxnRec& r = recs[slot];
+            if (r.cls == kNoReaction || !r.rev) continue;
+            const int j = r.prow;
+            double* d = &rxn_kc[slot * 16];
+            auto add = [&](int k, double nu) {
+                for (int q = 0; q < 7; ++q) {
+                    d[q] += nu * sp[k].lo[q];
+                    d[7 + q] += nu * sp[k].hi[q];
+                }
+            };
+            for (int k : prod[j]) add(k, 1.0);
+            for (int k : reac[j]) add(k, -1.0);
+            d[14] = sp[reac[j][0]].t_mid;
+        }
+    }
 
     // ---- one device allocation holding every table
     struct Part { const void* src; size_t bytes; size_t off; };
@@ -566,6 +596,7 @@ int load_mechanism(const char* path, pyro_mech** out) {
         {vown_tab.data(), vown_tab.size() * sizeof(int32_t), 0},
         {vn_own.data(), vn_own.size() * sizeof(int32_t), 0},
         {vpd_list.data(), vpd_list.size() * sizeof(int32_t), 0},
+        {rxn_kc.data(), rxn_kc.size() * sizeof(double), 0},
     };
     size_t total = 0;
     for (auto& p : parts) {
@@ -631,6 +662,7 @@ int load_mechanism(const char* path, pyro_mech** out) {
     v.own = reinterpret_cast<const int32_t*>(base + parts[19].off);
     v.n_own = reinterpret_cast<const int32_t*>(base + parts[20].off);
     v.pd_list = reinterpret_cast<const int32_t*>(base + parts[21].off);
+    d.rxn_kc = reinterpret_cast<const double*>(base + parts[22].off);
     err = prepare_production_rates(m);
     if (err == hipSuccess) err = prepare_vjp(m);
     if (err != hipSuccess) {

@@ -148,6 +148,9 @@ struct DevMech {
     // reverse sweep (VJP): its own schedule over kVjpWaves wavefronts
     DevSched vjp;
     const double* eff_t;                 // [S][n_pd] efficiencies by species
+    // reaction-equilibrium variant: per forward slot, the combined Gibbs
+    // coefficients sum_k nu_kj c_k (low range [7], high range [7], T_mid, 0)
+    const double* rxn_kc;                // [n_chunks][kWaves][kRxnPerWave][16]
     // surrogate
     int32_t E;                           // elements
     int32_t pad2;
@@ -164,6 +167,8 @@ struct pyro_mech {
     int max_pdw = 0;
     int vjp_max_own = 0;                 // the same for the reverse-sweep schedule
     int vjp_max_pdw = 0;
+    bool kc_ok = false;                  // every reaction's species share one T_mid
+    int wdot_variant = PYRO_WDOT_SPECIES_EQUILIBRIUM;
     int n_cu = 0;                        // compute units of the device
     std::vector<double> W;               // host copy
     std::vector<double> params;          // host copy of the default triples
@@ -203,7 +208,7 @@ hipError_t launch_internal_energy(const pyro_mech* m, int64_t n, int64_t ld,
                                   const double* T, const double* Y,
                                   double* e_out, hipStream_t stream);
 // LDS bytes the production-rate kernel needs for this mechanism.
-size_t production_rates_lds_bytes(const pyro_mech* m);
+size_t production_rates_lds_bytes(const pyro_mech* m, bool reaction_equilibrium);
 hipError_t prepare_production_rates(const pyro_mech* m);
 hipError_t launch_production_rates_vjp(const pyro_mech* m, int64_t n, int64_t ld,
                                        const double* rho, const double* T, const double* Y,

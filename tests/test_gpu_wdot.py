@@ -135,3 +135,62 @@ def test_wdot_full_size_sampled(lib_mechs):
                                     np.arange(n - 64, n)]))
     ws = w[:, torch.from_numpy(idx).cuda()].cpu().numpy()
     assert_wdot_parity(m, rho[idx], T[idx], Y[:, idx], ws)
+
+
+@pytest.fixture(scope="module")
+def cfg3_mech():
+    torch = torch_cuda()
+    import paper_2503_24286_amd as pyro
+    gm = pyro.Mechanism(mechs.config_path(3))
+    yield torch, pyro, gm
+    gm.close()
+
+
+@pytest.mark.parametrize("cfg,n", [(0, 1000), (1, 2000 + 45)])
+def test_both_equilibrium_variants_match_oracle(lib_mechs, cfg, n):
+    """The species-equilibrium (per-species exp(g/RT) in LDS) and the
+    reaction-equilibrium (combined coefficients, one exp per reversible
+    reaction) kernels both pass the parity bar."""
+    from paper_2503_24286_amd import _lib
+    torch, pyro, gms = lib_mechs
+    m = mechs.load_config(cfg)
+    gm = gms[cfg]
+    T, p, Y, rho = states(cfg, n, m.S, first=3333)
+    before = gm.wdot_variant
+    try:
+        for variant in (_lib.PYRO_WDOT_SPECIES_EQUILIBRIUM, _lib.PYRO_WDOT_REACTION_EQUILIBRIUM):
+            gm.wdot_variant = variant
+            assert gm.wdot_variant == variant
+            announce(f"wdot variant {variant} cfg{cfg} n={n}")
+            w = _run(torch, pyro, gm, rho, T, Y)
+            r = assert_wdot_parity(m, rho, T, Y, w)
+            announce(f"  max scaled {r['scaled'].max():.2e}")
+    finally:
+        gm.wdot_variant = before
+
+
+@pytest.mark.parametrize("n", [300, 64 * 5 + 17])
+def test_large_mechanism_matches_oracle(cfg3_mech, n):
+    """The 160-species, 900-reaction mechanism: its species rows do not fit
+    the LDS tile, so the loader selects the reaction-equilibrium kernel."""
+    from paper_2503_24286_amd import _lib
+    torch, pyro, gm = cfg3_mech
+    m = mechs.load_config(3)
+    assert gm.wdot_variant == _lib.PYRO_WDOT_REACTION_EQUILIBRIUM
+    T, p, Y, rho = states(3, n, m.S, first=100000)
+    announce(f"wdot cfg3 n={n}")
+    w = _run(torch, pyro, gm, rho, T, Y)
+    r = assert_wdot_parity(m, rho, T, Y, w)
+    announce(f"  max scaled {r['scaled'].max():.2e}")
+
+
+def test_variant_selection_errors(cfg3_mech):
+    from paper_2503_24286_amd import _lib
+    torch, pyro, gm = cfg3_mech
+    with pytest.raises(_lib.PyroError) as e:
+        gm.wdot_variant = _lib.PYRO_WDOT_SPECIES_EQUILIBRIUM
+    assert e.value.code == _lib.PYRO_E_UNSUPPORTED
+    with pytest.raises(_lib.PyroError) as e:
+        gm.wdot_variant = 7
+    assert e.value.code == _lib.PYRO_E_ARG
+    assert gm.wdot_variant == _lib.PYRO_WDOT_REACTION_EQUILIBRIUM
