@@ -14,13 +14,15 @@ timed after the steps ("roofline_other"): algorithmic FP64 flops per launch
 over the average launch time, timed with HIP events on the stream they run
 on; and the CPU oracle timed on a bounded sample of the same workload.
 
-A second object, "surrogate", reports the learned surrogate on the same
-mechanism: its training on exact-kernel labels, and for each target error the
-calibrated thresholds, the fallback fraction, the error percentiles against
-the exact kernel and the speed against the exact kernel alone.
+"large_mechanism" times the production rates of the 160-species,
+900-reaction mechanism on 2^20 cells.  "surrogate" reports the learned
+surrogate on the 53-species mechanism: its training on exact-kernel labels,
+and for each target error the calibrated thresholds, the fallback fraction,
+the error percentiles against the exact kernel and the speed against the
+exact kernel alone.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--cells N]
-                       [--no-cpu-baseline] [--cpu-sample N] [--no-surrogate]
+                       [--no-cpu-baseline] [--cpu-sample N] [--no-surrogate] [--no-large]
                        [--train-states N] [--members E] [--hidden H]
                        [--epochs K] [--batch B] [--lr LR] [--targets ...]
 """
@@ -165,6 +167,43 @@ def _time_ms(fn, reps, stream):
     return a.elapsed_time(b) / reps
 
 
+def large_mechanism_leg(args, log):
+    """The 160-species, 900-reaction mechanism (2^20 cells, states drawn as
+    for the 53-species workload): production rates alone, with the kernel
+    variant the loader selects (its species rows do not fit the LDS tile)."""
+    import numpy as np
+    import torch
+
+    import paper_2503_24286_amd as pyro
+    from paper_2503_24286_amd import surrogate as sur
+
+    gm = pyro.Mechanism(os.path.join(REPO, "mechanisms", "cfg3.pyromech"))
+    n = 1 << 20
+    T = np.empty(n)
+    p = np.empty(n)
+    Y = np.empty((gm.n_species, n))
+    for a, Tc, pc, Yc in sur.draw_chunks(3, n, gm.n_species, None, threads=args.threads):
+        T[a:a + Tc.shape[0]], p[a:a + Tc.shape[0]], Y[:, a:a + Tc.shape[0]] = Tc, pc, Yc
+    Td, pd, Yd = (torch.from_numpy(x).cuda() for x in (T, p, Y))
+    rho = pyro.density(gm, pd, Td, Yd)
+    w = torch.empty_like(Yd)
+    stream = torch.cuda.current_stream()
+    ms = _time_ms(lambda: pyro.production_rates(gm, rho, Td, Yd, out=w), args.reps, stream)
+    if not bool(torch.isfinite(w).all()):
+        raise RuntimeError("non-finite rates on the large mechanism")
+    fpc = wdot_flops_per_cell(gm)
+    achieved = fpc * n / (ms * 1e-3) / 1e12
+    out = {"workload": f"{gm.n_species}-species {gm.n_reactions}-reaction synthetic mechanism, "
+                       f"{n} cells", "variant": "reaction-equilibrium" if gm.wdot_variant
+                       else "species-equilibrium",
+           "ms": round(ms, 4), "Mcells_s": round(n / ms / 1e3, 3), "flops_per_cell": fpc,
+           "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS,
+                        "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4)}}
+    log(f"large mechanism: {out['Mcells_s']} Mcells/s")
+    gm.close()
+    return out
+
+
 def surrogate_leg(args, log):
     """Config-4 surrogate: train an ensemble on exact-kernel labels of
     ``--train-states`` seeded states with the library's own BF16 kernels,
@@ -281,6 +320,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=1 << 19,
                     help="cells for the oracle's Newton + omega (the VJP uses 1/64 of them)")
     ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the 160-species mechanism's production-rate line")
     ap.add_argument("--train-states", type=int, default=1 << 24)
     ap.add_argument("--members", type=int, default=2)
     ap.add_argument("--hidden", type=int, default=256)
@@ -411,9 +452,11 @@ def main():
     gm.close()
     del T_d, p_d, Y_d, rho, e, T_out, status, w, wbar, Ybar, Tbar, pbar
     torch.cuda.empty_cache()
+    def log(msg):
+        print(f"# {msg}", file=sys.stderr, flush=True)
+    if not args.no_large:
+        result["large_mechanism"] = large_mechanism_leg(args, log)
     if not args.no_surrogate:
-        def log(msg):
-            print(f"# {msg}", file=sys.stderr, flush=True)
         result["surrogate"] = surrogate_leg(args, log)
     if args.calibration_copy > 0:
         src = torch.empty(args.calibration_copy << 17, dtype=torch.float64, device="cuda")

@@ -425,9 +425,12 @@ __global__ __launch_bounds__(kVjpWaves * 64) void vjp_kernel(
                     for (; j < m.n_pd; ++j) cm = fma(et[j], mbar[size_t(j) * kTile + lane], cm);
                     cm += (c1 + c2) + c3;
                 }
-                const double yk = Y[size_t(k) * ld + c];
+                // dL/dY_k = Cbar_k rho/W_k = (Cbar_k C_k) rho/(W_k C_k), with C_k
+                // still in this tile's LDS row (zero where Y_k <= 0)
+                const double ck = reinterpret_cast<const double*>(lds + k * kVRow)[lane];
                 const SpeciesRec sp = cst(m.species)[k];
-                const double ybar = yk > 0.0 ? cc[i] / yk + rc * sp.inv_w * cm : 0.0;
+                const double rw = rc * sp.inv_w;
+                const double ybar = ck > 0.0 ? cc[i] * rw / ck + rw * cm : 0.0;
                 const NewtonSpecies ns = cst(m.newton)[k];
                 const double h_lo = enthalpy_poly(ns.lo, cs.T, cs.invT);
                 const double h_hi = enthalpy_poly(ns.hi, cs.T, cs.invT);
