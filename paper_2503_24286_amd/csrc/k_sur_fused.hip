@@ -231,14 +231,26 @@ __global__ __launch_bounds__(waves_per_block(E) * 64) void fused_kernel(
     const int64_t c = valid ? cell : n - 1;
 
     // ---- features of the 32 cells, staged in this wave's LDS rows; lane
-    // half h converts the species k = h, h + 2, ...
+    // half h converts the species k = h, h + 2, ...  All of the lane's mass
+    // fractions are loaded before any is used (one memory latency per wave
+    // instead of one per species: this phase runs at the MLP's occupancy).
+    constexpr int kHalfSpecies = (kFeatPad - 2) / 2;   // species per lane half
     uint16_t* fr = feat + cl * kFeatRow;
     const double Tc = T[c];
+    double yv[kHalfSpecies];
+#pragma unroll
+    for (int i = 0; i < kHalfSpecies; ++i) {
+        const int k = h + 2 * i;
+        yv[i] = k < m.S ? Y[size_t(k) * ld + c] : 0.0;
+    }
     double x = 0.0;  // partial 1/W
-    for (int k = h; k < m.S; k += 2) {
-        const double y = Y[size_t(k) * ld + c];
-        x = fma(y, m.newton[k].inv_w, x);
-        fr[k + 2] = f2bf(float((log(fmax(y, 0.0) + 1e-12) - a.shift[k + 2]) * a.scale[k + 2]));
+#pragma unroll
+    for (int i = 0; i < kHalfSpecies; ++i) {
+        const int k = h + 2 * i;
+        if (k < m.S) {
+            x = fma(yv[i], m.newton[k].inv_w, x);
+            fr[k + 2] = f2bf(float((log(fmax(yv[i], 0.0) + 1e-12) - a.shift[k + 2]) * a.scale[k + 2]));
+        }
     }
     x += __shfl_xor(x, 32);
     if (h == 0) {
