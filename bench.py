@@ -175,6 +175,7 @@ def large_mechanism_leg(args, log):
     import torch
 
     import paper_2503_24286_amd as pyro
+    from paper_2503_24286_amd import _lib
     from paper_2503_24286_amd import surrogate as sur
 
     gm = pyro.Mechanism(os.path.join(REPO, "mechanisms", "cfg3.pyromech"))
@@ -191,12 +192,19 @@ def large_mechanism_leg(args, log):
     ms = _time_ms(lambda: pyro.production_rates(gm, rho, Td, Yd, out=w), args.reps, stream)
     if not bool(torch.isfinite(w).all()):
         raise RuntimeError("non-finite rates on the large mechanism")
+    # the third-body concentrations (a dense contraction) on the FP64 matrix
+    # cores instead of the FMA units
+    base = gm.wdot_variant
+    gm.wdot_variant = base | _lib.PYRO_WDOT_MFMA_THIRD_BODY
+    ms_mfma = _time_ms(lambda: pyro.production_rates(gm, rho, Td, Yd, out=w), args.reps, stream)
+    gm.wdot_variant = base
     fpc = wdot_flops_per_cell(gm)
     achieved = fpc * n / (ms * 1e-3) / 1e12
     out = {"workload": f"{gm.n_species}-species {gm.n_reactions}-reaction synthetic mechanism, "
                        f"{n} cells", "variant": "reaction-equilibrium" if gm.wdot_variant
                        else "species-equilibrium",
            "ms": round(ms, 4), "Mcells_s": round(n / ms / 1e3, 3), "flops_per_cell": fpc,
+           "third_body_on_mfma_ms": round(ms_mfma, 4),
            "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS,
                         "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4)}}
     log(f"large mechanism: {out['Mcells_s']} Mcells/s")
@@ -404,6 +412,19 @@ def main():
     w2 = torch.empty_like(w)
     wdot_ms = _time_ms(lambda: pyro.production_rates(gm, rho, T_out, Y_d, out=w2),
                        max(args.steps, 3), stream)
+    # the same with each alternative kernel variant (equilibrium constants per
+    # reaction; third-body concentrations on the FP64 matrix cores)
+    from paper_2503_24286_amd import _lib
+    variant_ms = {}
+    default_variant = gm.wdot_variant
+    for name, v in (("reaction_equilibrium", _lib.PYRO_WDOT_REACTION_EQUILIBRIUM),
+                    ("third_body_on_mfma", default_variant | _lib.PYRO_WDOT_MFMA_THIRD_BODY),
+                    ("reaction_equilibrium_third_body_on_mfma",
+                     _lib.PYRO_WDOT_REACTION_EQUILIBRIUM | _lib.PYRO_WDOT_MFMA_THIRD_BODY)):
+        gm.wdot_variant = v
+        variant_ms[name] = round(_time_ms(
+            lambda: pyro.production_rates(gm, rho, T_out, Y_d, out=w2), 3, stream), 4)
+    gm.wdot_variant = default_variant
     del w2
 
     ms_per_step = total_ms / args.steps
@@ -443,7 +464,8 @@ def main():
         },
         "kernels_ms": {"vjp_with_wdot": round(fused_ms, 4),
                        "newton_and_rest": round(ms_per_step - fused_ms, 4),
-                       "wdot_alone_outside_step": round(wdot_ms, 4)},
+                       "wdot_alone_outside_step": round(wdot_ms, 4),
+                       "wdot_variants_outside_step": variant_ms},
         "roofline": roof("vjp_kernel", fused_ms, fused_flops_per_cell(gm),
                          fused_bytes_per_cell(gm)),
         "roofline_other": roof("wdot_f64_kernel", wdot_ms, wdot_flops_per_cell(gm),

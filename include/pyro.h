@@ -71,7 +71,12 @@ enum pyro_wdot_variant {
     /* per reaction exp(sum_k nu_kj g0_k/RT) from coefficients combined at
      * load time: one exponential per reversible reaction, 512 B of LDS per
      * species; needs every reaction's species to share one NASA7 T_mid */
-    PYRO_WDOT_REACTION_EQUILIBRIUM = 1
+    PYRO_WDOT_REACTION_EQUILIBRIUM = 1,
+    /* flag, combinable with either: the third-body concentrations
+     * [M]_j = sum_k eps_jk C_k (a dense contraction) of a 64-cell tile on the
+     * FP64 matrix cores (v_mfma_f64_16x16x4f64) instead of per-wave FMA
+     * passes; [M] is then held in LDS (512 B per third-body reaction) */
+    PYRO_WDOT_MFMA_THIRD_BODY = 2
 };
 
 typedef struct pyro_mech pyro_mech;
@@ -109,7 +114,8 @@ PYRO_API const char* pyro_last_error(void);
 PYRO_API int pyro_mech_load(const char* path, pyro_mech** out);
 PYRO_API void pyro_mech_free(pyro_mech* mech);
 PYRO_API int pyro_mech_get_info(const pyro_mech* mech, pyro_mech_info* info);
-/* Selects the production-rate kernel variant (enum pyro_wdot_variant) used by
+/* Selects the production-rate kernel variant (enum pyro_wdot_variant, an
+ * equilibrium variant optionally or-ed with PYRO_WDOT_MFMA_THIRD_BODY) used by
  * pyro_production_rates and the surrogate's fallback.  The loader picks the
  * species variant when its LDS tile fits and the reaction variant otherwise;
  * PYRO_E_UNSUPPORTED if the requested variant cannot run this mechanism.

@@ -23,6 +23,7 @@ PYRO_F64 = 0
 PYRO_F32 = 1
 PYRO_WDOT_SPECIES_EQUILIBRIUM = 0
 PYRO_WDOT_REACTION_EQUILIBRIUM = 1
+PYRO_WDOT_MFMA_THIRD_BODY = 2
 
 
 class PyroError(RuntimeError):

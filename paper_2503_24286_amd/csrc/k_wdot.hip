@@ -34,6 +34,12 @@
 // then k exp(dg_j) (R T/p0)^dnu prod_p C_p with one exponential per
 // reversible reaction, and LDS holds C only (half the bytes per species),
 // which lets large mechanisms fit and raises occupancy.
+//
+// MFMA third-body variant (MM): [M]_j = sum_k eps_jk C_k is a dense
+// contraction (every species has an efficiency), computed for the whole tile
+// as M[64 cells x n_pd] = C[64 x S] eps^T[S x n_pd] with v_mfma_f64_16x16x4f64
+// (A = C from the LDS rows, B = pre-packed eps^T fragments), written to LDS
+// once per tile; the waves then read [M] of their reactions from there.
 #include "pyro_internal.h"
 
 namespace pyro {
@@ -183,7 +189,9 @@ __device__ inline double rate_of_progress(const DevMech& m, const RxnRec& r,
     return q;
 }
 
-template <int MAXOWN, int MAXPD, bool RKC>
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+template <int MAXOWN, int MAXPD, bool RKC, bool MM>
 __global__ __launch_bounds__(kWaves * 64) void wdot_f64_kernel(
     DevMech m, int64_t n, int64_t ld, const double* __restrict__ rho,
     const double* __restrict__ T, const double* __restrict__ Y,
@@ -239,14 +247,39 @@ __global__ __launch_bounds__(kWaves * 64) void wdot_f64_kernel(
     }
     __syncthreads();
 
+    constexpr int rowb = RKC ? kRowC : kRow;
+    unsigned char* qbase = lds + size_t(m.S) * rowb;
+    double* Ml = reinterpret_cast<double*>(qbase + 2 * kQBuf);  // MM: [n_pd16][64]
+    if constexpr (MM) {
+        // ---- the tile's third-body concentrations on the matrix cores: wave w
+        // takes the 16-cell x 16-reaction output blocks w, w + 8, ...
+        const int n_pb = (m.n_pd + 15) / 16, n_ks = (m.S + 3) / 4;
+        for (int t = w; t < 4 * n_pb; t += kWaves) {
+            const int cb = t & 3, pb = t >> 2;
+            const double* eb = m.eps_frag + size_t(pb) * n_ks * 64 + lane;
+            d4 acc = {0.0, 0.0, 0.0, 0.0};
+            for (int kk = 0; kk < n_ks; ++kk) {
+                const int k = 4 * kk + (lane >> 4);
+                const double a = k < m.S
+                    ? reinterpret_cast<const double*>(lds + k * rowb)[16 * cb + (lane & 15)] : 0.0;
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, eb[size_t(kk) * 64], acc, 0, 0, 0);
+            }
+            // D: register i of lane l is cell 4 i + l/16, reaction l % 16 of the block
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                Ml[(16 * pb + (lane & 15)) * kTile + 16 * cb + 4 * i + (lane >> 4)] = acc[i];
+        }
+        __syncthreads();
+    }
+
     // ---- third-body concentrations of this wave's reactions
     double Mr[MAXPD];
 #pragma unroll
     for (int i = 0; i < MAXPD; ++i) Mr[i] = 0.0;
-    if (m.n_pdw[w] > 0) {
+    if (!MM && m.n_pdw[w] > 0) {
         const double* ew = m.effw + size_t(w) * m.S * kMaxPd;
         for (int k = 0; k < m.S; ++k) {
-            const double ck = reinterpret_cast<const double*>(lds + k * (RKC ? kRowC : kRow))[lane];
+            const double ck = reinterpret_cast<const double*>(lds + k * rowb)[lane];
 #pragma unroll
             for (int i = 0; i < MAXPD; ++i) Mr[i] = fma(ew[k * kMaxPd + i], ck, Mr[i]);
         }
@@ -256,7 +289,6 @@ __global__ __launch_bounds__(kWaves * 64) void wdot_f64_kernel(
     double acc[MAXOWN];
 #pragma unroll
     for (int i = 0; i < MAXOWN; ++i) acc[i] = 0.0;
-    unsigned char* qbase = lds + size_t(m.S) * (RKC ? kRowC : kRow);
     static_assert(kRxnPerWave == 2, "the reaction phase handles reactions in pairs");
     for (int ch = 0; ch < m.n_chunks; ++ch) {
         unsigned char* qb = qbase + (ch & 1) * kQBuf;
@@ -267,8 +299,14 @@ __global__ __launch_bounds__(kWaves * 64) void wdot_f64_kernel(
         const double kf0 = exp(log_arrhenius(params, r0.prow, lnT, invRT));
         const double kf1 = exp(log_arrhenius(params, r1.prow, lnT, invRT));
         // the wave meets its third-body/falloff reactions in queue order
-        const double M0 = r0.cls >= kThirdBody ? pop_front(Mr) : 1.0;
-        const double M1 = r1.cls >= kThirdBody ? pop_front(Mr) : 1.0;
+        double M0 = 1.0, M1 = 1.0;
+        if constexpr (MM) {
+            if (r0.cls >= kThirdBody) M0 = Ml[r0.pd * kTile + lane];
+            if (r1.cls >= kThirdBody) M1 = Ml[r1.pd * kTile + lane];
+        } else {
+            M0 = r0.cls >= kThirdBody ? pop_front(Mr) : 1.0;
+            M1 = r1.cls >= kThirdBody ? pop_front(Mr) : 1.0;
+        }
         const cptr<double> kc = cst(m.rxn_kc) + (size_t(ch) * kWaves + w) * kRxnPerWave * 16;
         if (r0.cls != kNoReaction)
             *reinterpret_cast<double*>(qb + r0.qoff + lane * 8) = rate_of_progress<RKC>(
@@ -313,59 +351,81 @@ __global__ __launch_bounds__(kWaves * 64) void wdot_f64_kernel(
     }
 }
 
-template <int MAXOWN, int MAXPD, bool RKC>
+template <int MAXOWN, int MAXPD, bool RKC, bool MM>
 hipError_t launch_f64(const pyro_mech* m, int64_t n, int64_t ld, const double* rho,
                       const double* T, const double* Y, double* wdot,
                       const double* params, hipStream_t stream, const int64_t* n_dev) {
-    const size_t lds = production_rates_lds_bytes(m, RKC);
+    const size_t lds = production_rates_lds_bytes(m, RKC, MM);
     const int64_t blocks = (n + kTile - 1) / kTile;
-    hipLaunchKernelGGL((wdot_f64_kernel<MAXOWN, MAXPD, RKC>), dim3(unsigned(blocks)),
+    hipLaunchKernelGGL((wdot_f64_kernel<MAXOWN, MAXPD, RKC, MM>), dim3(unsigned(blocks)),
                        dim3(kWaves * 64), lds, stream, m->dev, n, ld, rho, T, Y, wdot,
                        params ? params : m->dev.params, n_dev);
     return hipGetLastError();
 }
 
 // Kernel instances: (species owned per wave, [M] slots per wave, variant).
-template <int MAXOWN, int MAXPD, bool RKC>
+template <int MAXOWN, int MAXPD, bool RKC, bool MM>
 hipError_t set_lds(int bytes) {
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(&wdot_f64_kernel<MAXOWN, MAXPD, RKC>),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    return hipFuncSetAttribute(
+        reinterpret_cast<const void*>(&wdot_f64_kernel<MAXOWN, MAXPD, RKC, MM>),
+        hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
-template <int MAXPD, bool RKC>
+template <int MAXPD, bool RKC, bool MM>
 hipError_t dispatch_own(const pyro_mech* m, int64_t n, int64_t ld, const double* r,
                         const double* t, const double* y, double* o, const double* params,
                         hipStream_t stream, const int64_t* nd) {
-    if (m->max_own <= 8) return launch_f64<8, MAXPD, RKC>(m, n, ld, r, t, y, o, params, stream, nd);
-    if (m->max_own <= 16) return launch_f64<16, MAXPD, RKC>(m, n, ld, r, t, y, o, params, stream, nd);
-    if (m->max_own <= 32) return launch_f64<32, MAXPD, RKC>(m, n, ld, r, t, y, o, params, stream, nd);
-    return launch_f64<64, MAXPD, RKC>(m, n, ld, r, t, y, o, params, stream, nd);
+    if (m->max_own <= 8) return launch_f64<8, MAXPD, RKC, MM>(m, n, ld, r, t, y, o, params, stream, nd);
+    if (m->max_own <= 16) return launch_f64<16, MAXPD, RKC, MM>(m, n, ld, r, t, y, o, params, stream, nd);
+    if (m->max_own <= 32) return launch_f64<32, MAXPD, RKC, MM>(m, n, ld, r, t, y, o, params, stream, nd);
+    return launch_f64<64, MAXPD, RKC, MM>(m, n, ld, r, t, y, o, params, stream, nd);
 }
 
-template <bool RKC>
+template <bool RKC, bool MM>
 hipError_t set_lds_variant(int bytes) {
     hipError_t e = hipSuccess;
+    // the MFMA variant holds no per-wave [M] slots: one MAXPD instance
     const hipError_t all[] = {
-        set_lds<8, 8, RKC>(bytes),   set_lds<16, 8, RKC>(bytes),  set_lds<32, 8, RKC>(bytes),
-        set_lds<64, 8, RKC>(bytes),  set_lds<8, 16, RKC>(bytes),  set_lds<16, 16, RKC>(bytes),
-        set_lds<32, 16, RKC>(bytes), set_lds<64, 16, RKC>(bytes)};
+        set_lds<8, 8, RKC, MM>(bytes),  set_lds<16, 8, RKC, MM>(bytes),
+        set_lds<32, 8, RKC, MM>(bytes), set_lds<64, 8, RKC, MM>(bytes),
+        MM ? hipSuccess : set_lds<8, 16, RKC, MM>(bytes),
+        MM ? hipSuccess : set_lds<16, 16, RKC, MM>(bytes),
+        MM ? hipSuccess : set_lds<32, 16, RKC, MM>(bytes),
+        MM ? hipSuccess : set_lds<64, 16, RKC, MM>(bytes)};
     for (hipError_t x : all)
         if (x != hipSuccess) e = x;
     return e;
 }
 
+template <bool RKC, bool MM>
+hipError_t dispatch_variant(const pyro_mech* m, int64_t n, int64_t ld, const double* r,
+                            const double* t, const double* y, double* o, const double* params,
+                            hipStream_t stream, const int64_t* nd) {
+    if (MM || m->max_pdw <= 8) return dispatch_own<8, RKC, MM>(m, n, ld, r, t, y, o, params, stream, nd);
+    return dispatch_own<16, RKC, MM>(m, n, ld, r, t, y, o, params, stream, nd);
+}
+
 }  // namespace
 
-size_t production_rates_lds_bytes(const pyro_mech* m, bool reaction_equilibrium) {
-    return size_t(m->S) * (reaction_equilibrium ? kRowC : kRow) + 2 * size_t(kQBuf);
+size_t production_rates_lds_bytes(const pyro_mech* m, bool reaction_equilibrium,
+                                  bool mfma_third_body) {
+    return size_t(m->S) * (reaction_equilibrium ? kRowC : kRow) + 2 * size_t(kQBuf) +
+           (mfma_third_body ? size_t((m->n_tb + m->n_fo + 15) / 16 * 16) * kTile * 8 : 0);
 }
 
 hipError_t prepare_production_rates(const pyro_mech* m) {
     hipError_t e = hipSuccess;
-    for (const bool rkc : {false, true}) {
-        const size_t bytes = production_rates_lds_bytes(m, rkc);
+    for (const int v : {0, 1, 2, 3}) {
+        const bool rkc = v & 1, mm = v & 2;
+        const size_t bytes = production_rates_lds_bytes(m, rkc, mm);
         if (bytes > 160 * 1024 || (rkc && !m->kc_ok)) continue;
-        const hipError_t x = rkc ? set_lds_variant<true>(int(bytes)) : set_lds_variant<false>(int(bytes));
+        hipError_t x;
+        switch (v) {
+            case 0: x = set_lds_variant<false, false>(int(bytes)); break;
+            case 1: x = set_lds_variant<true, false>(int(bytes)); break;
+            case 2: x = set_lds_variant<false, true>(int(bytes)); break;
+            default: x = set_lds_variant<true, true>(int(bytes));
+        }
         if (x != hipSuccess) e = x;
     }
     return e;
@@ -380,12 +440,16 @@ hipError_t launch_production_rates(const pyro_mech* m, int64_t n, int64_t ld, in
     const double* t = static_cast<const double*>(T);
     const double* y = static_cast<const double*>(Y);
     double* o = static_cast<double*>(wdot);
-    if (m->wdot_variant == PYRO_WDOT_REACTION_EQUILIBRIUM) {
-        if (m->max_pdw <= 8) return dispatch_own<8, true>(m, n, ld, r, t, y, o, params, stream, n_dev);
-        return dispatch_own<16, true>(m, n, ld, r, t, y, o, params, stream, n_dev);
+    switch (m->wdot_variant) {
+        case PYRO_WDOT_REACTION_EQUILIBRIUM:
+            return dispatch_variant<true, false>(m, n, ld, r, t, y, o, params, stream, n_dev);
+        case PYRO_WDOT_MFMA_THIRD_BODY:
+            return dispatch_variant<false, true>(m, n, ld, r, t, y, o, params, stream, n_dev);
+        case PYRO_WDOT_REACTION_EQUILIBRIUM | PYRO_WDOT_MFMA_THIRD_BODY:
+            return dispatch_variant<true, true>(m, n, ld, r, t, y, o, params, stream, n_dev);
+        default:
+            return dispatch_variant<false, false>(m, n, ld, r, t, y, o, params, stream, n_dev);
     }
-    if (m->max_pdw <= 8) return dispatch_own<8, false>(m, n, ld, r, t, y, o, params, stream, n_dev);
-    return dispatch_own<16, false>(m, n, ld, r, t, y, o, params, stream, n_dev);
 }
 
 }  // namespace pyro

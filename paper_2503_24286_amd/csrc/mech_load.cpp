@@ -550,6 +550,16 @@ int load_mechanism(const char* path, pyro_mech** out) {
             vpd_list[w * kMaxPd + i] = pd_row[bw.pd_of_wave[w][i]];
     std::vector<double> params = m->params;
     if (params.empty()) params.push_back(0.0);
+    // B fragments of eps^T for the MFMA third-body variant
+    const int n_pb = (n_pd + 15) / 16, n_ks = (S + 3) / 4;
+    std::vector<double> eps_frag(std::max(size_t(1), size_t(n_pb) * n_ks * 64), 0.0);
+    for (int pb = 0; pb < n_pb; ++pb)
+        for (int kk = 0; kk < n_ks; ++kk)
+            for (int l = 0; l < 64; ++l) {
+                const int j = 16 * pb + (l & 15), k = 4 * kk + (l >> 4);
+                if (j < n_pd && k < S)
+                    eps_frag[(size_t(pb) * n_ks + kk) * 64 + l] = f.eff[size_t(j) * S + k];
+            }
     // combined Gibbs coefficients of every reversible reaction, per forward
     // slot: sum_k nu_kj c_k for both ranges, then T_mid (g0/RT is linear in c)
     std::vector<double> rxn_kc(recs.size() * 16, 0.0);
@@ -597,6 +607,7 @@ int load_mechanism(const char* path, pyro_mech** out) {
         {vn_own.data(), vn_own.size() * sizeof(int32_t), 0},
         {vpd_list.data(), vpd_list.size() * sizeof(int32_t), 0},
         {rxn_kc.data(), rxn_kc.size() * sizeof(double), 0},
+        {eps_frag.data(), eps_frag.size() * sizeof(double), 0},
     };
     size_t total = 0;
     for (auto& p : parts) {
@@ -663,6 +674,7 @@ int load_mechanism(const char* path, pyro_mech** out) {
     v.n_own = reinterpret_cast<const int32_t*>(base + parts[20].off);
     v.pd_list = reinterpret_cast<const int32_t*>(base + parts[21].off);
     d.rxn_kc = reinterpret_cast<const double*>(base + parts[22].off);
+    d.eps_frag = reinterpret_cast<const double*>(base + parts[23].off);
     err = prepare_production_rates(m);
     if (err == hipSuccess) err = prepare_vjp(m);
     if (err != hipSuccess) {

@@ -151,6 +151,9 @@ struct DevMech {
     // reaction-equilibrium variant: per forward slot, the combined Gibbs
     // coefficients sum_k nu_kj c_k (low range [7], high range [7], T_mid, 0)
     const double* rxn_kc;                // [n_chunks][kWaves][kRxnPerWave][16]
+    // MFMA third-body variant: B fragments of eps^T, [pd block][K-step][lane]
+    // = eps[16 pb + l%16][4 kk + l/16] (zero outside n_pd x S)
+    const double* eps_frag;
     // surrogate
     int32_t E;                           // elements
     int32_t pad2;
@@ -208,7 +211,8 @@ hipError_t launch_internal_energy(const pyro_mech* m, int64_t n, int64_t ld,
                                   const double* T, const double* Y,
                                   double* e_out, hipStream_t stream);
 // LDS bytes the production-rate kernel needs for this mechanism.
-size_t production_rates_lds_bytes(const pyro_mech* m, bool reaction_equilibrium);
+size_t production_rates_lds_bytes(const pyro_mech* m, bool reaction_equilibrium,
+                                  bool mfma_third_body = false);
 hipError_t prepare_production_rates(const pyro_mech* m);
 hipError_t launch_production_rates_vjp(const pyro_mech* m, int64_t n, int64_t ld,
                                        const double* rho, const double* T, const double* Y,

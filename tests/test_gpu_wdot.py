@@ -150,7 +150,8 @@ def cfg3_mech():
 def test_both_equilibrium_variants_match_oracle(lib_mechs, cfg, n):
     """The species-equilibrium (per-species exp(g/RT) in LDS) and the
     reaction-equilibrium (combined coefficients, one exp per reversible
-    reaction) kernels both pass the parity bar."""
+    reaction) kernels, each with the third-body concentrations on the FMA
+    units or on the FP64 matrix cores, all pass the parity bar."""
     from paper_2503_24286_amd import _lib
     torch, pyro, gms = lib_mechs
     m = mechs.load_config(cfg)
@@ -158,7 +159,9 @@ def test_both_equilibrium_variants_match_oracle(lib_mechs, cfg, n):
     T, p, Y, rho = states(cfg, n, m.S, first=3333)
     before = gm.wdot_variant
     try:
-        for variant in (_lib.PYRO_WDOT_SPECIES_EQUILIBRIUM, _lib.PYRO_WDOT_REACTION_EQUILIBRIUM):
+        for variant in (_lib.PYRO_WDOT_SPECIES_EQUILIBRIUM, _lib.PYRO_WDOT_REACTION_EQUILIBRIUM,
+                        _lib.PYRO_WDOT_SPECIES_EQUILIBRIUM | _lib.PYRO_WDOT_MFMA_THIRD_BODY,
+                        _lib.PYRO_WDOT_REACTION_EQUILIBRIUM | _lib.PYRO_WDOT_MFMA_THIRD_BODY):
             gm.wdot_variant = variant
             assert gm.wdot_variant == variant
             announce(f"wdot variant {variant} cfg{cfg} n={n}")
@@ -178,10 +181,16 @@ def test_large_mechanism_matches_oracle(cfg3_mech, n):
     m = mechs.load_config(3)
     assert gm.wdot_variant == _lib.PYRO_WDOT_REACTION_EQUILIBRIUM
     T, p, Y, rho = states(3, n, m.S, first=100000)
-    announce(f"wdot cfg3 n={n}")
-    w = _run(torch, pyro, gm, rho, T, Y)
-    r = assert_wdot_parity(m, rho, T, Y, w)
-    announce(f"  max scaled {r['scaled'].max():.2e}")
+    try:
+        for variant in (_lib.PYRO_WDOT_REACTION_EQUILIBRIUM,
+                        _lib.PYRO_WDOT_REACTION_EQUILIBRIUM | _lib.PYRO_WDOT_MFMA_THIRD_BODY):
+            gm.wdot_variant = variant
+            announce(f"wdot cfg3 variant {variant} n={n}")
+            w = _run(torch, pyro, gm, rho, T, Y)
+            r = assert_wdot_parity(m, rho, T, Y, w)
+            announce(f"  max scaled {r['scaled'].max():.2e}")
+    finally:
+        gm.wdot_variant = _lib.PYRO_WDOT_REACTION_EQUILIBRIUM
 
 
 def test_variant_selection_errors(cfg3_mech):
@@ -192,5 +201,8 @@ def test_variant_selection_errors(cfg3_mech):
     assert e.value.code == _lib.PYRO_E_UNSUPPORTED
     with pytest.raises(_lib.PyroError) as e:
         gm.wdot_variant = 7
+    assert e.value.code == _lib.PYRO_E_ARG
+    with pytest.raises(_lib.PyroError) as e:
+        gm.wdot_variant = -1
     assert e.value.code == _lib.PYRO_E_ARG
     assert gm.wdot_variant == _lib.PYRO_WDOT_REACTION_EQUILIBRIUM
