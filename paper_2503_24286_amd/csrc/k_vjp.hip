@@ -30,7 +30,7 @@
 namespace pyro {
 namespace {
 
-constexpr int kVRow = kTile * 24;                   // C[64], G[64], wbar[64]
+constexpr int kVRow = kVjpRow;                      // C[64], G[64], wbar[64]
 constexpr int kPlane = kChunk * kTile * 8;          // a, b or q: [slot][cell]
 static_assert(kVjpWaves == kChunk, "one reaction per wavefront fills a chunk's slots");
 
@@ -38,8 +38,9 @@ struct CGW {
     double c, g, w;
 };
 
-__device__ inline CGW lds_row(const unsigned char* lds, int k, int lane) {
-    const double* p = reinterpret_cast<const double*>(lds + k * kVRow) + lane;
+// row_off: byte offset of the species row (species * kVRow)
+__device__ inline CGW lds_row(const unsigned char* lds, int row_off, int lane) {
+    const double* p = reinterpret_cast<const double*>(lds + row_off) + lane;
     return CGW{p[0], p[kTile], p[2 * kTile]};
 }
 
@@ -59,6 +60,19 @@ __device__ inline double gibbs_poly(const double* c, double T, double omlnT, dou
 __device__ inline double enthalpy_poly(const double* a, double T, double invT) {
     return a[0] + a[5] * invT +
            T * (a[1] * 0.5 + T * (a[2] * (1.0 / 3.0) + T * (a[3] * 0.25 + T * (a[4] * 0.2))));
+}
+
+// A gathering entry: slot byte offset and the coefficients nu', -nu'' and
+// nu' - nu'' rebuilt from the upper 16 bits of their doubles (wave-uniform,
+// so they stay scalar operands of the FMAs; no conversions)
+struct GatherCoef {
+    int off;
+    double nf, mnr, d;
+};
+
+__device__ inline GatherCoef gather_coef(uint32_t w0, uint32_t w1) {
+    return GatherCoef{int(w0 & 0xffffu), from_top16(w0 >> 16), from_top16(w1 & 0xffffu),
+                      from_top16(w1 >> 16)};
 }
 
 template <int N>
@@ -126,29 +140,29 @@ __device__ inline RevOut reaction_vjp(const DevMech& m, const RxnRec& r,
         s = ipr + dlnF_dlnPr;
     }
     // forward products and the sum of nu wbar over the participants
-    CGW x = lds_row(lds, r.r[0] / (kTile * 16), lane);
+    CGW x = lds_row(lds, r.r[0], lane);
     double cr = x.c, gr = x.g, qbar = -x.w;
     if (r.nr > 1) {
-        x = lds_row(lds, r.r[1] / (kTile * 16), lane);
+        x = lds_row(lds, r.r[1], lane);
         cr *= x.c;
         gr *= x.g;
         qbar -= x.w;
         if (r.nr > 2) {
-            x = lds_row(lds, r.r[2] / (kTile * 16), lane);
+            x = lds_row(lds, r.r[2], lane);
             cr *= x.c;
             gr *= x.g;
             qbar -= x.w;
         }
     }
-    x = lds_row(lds, r.p[0] / (kTile * 16), lane);
+    x = lds_row(lds, r.p[0], lane);
     double cgp = x.c * x.g;
     qbar += x.w;
     if (r.np > 1) {
-        x = lds_row(lds, r.p[1] / (kTile * 16), lane);
+        x = lds_row(lds, r.p[1], lane);
         cgp *= x.c * x.g;
         qbar += x.w;
         if (r.np > 2) {
-            x = lds_row(lds, r.p[2] / (kTile * 16), lane);
+            x = lds_row(lds, r.p[2], lane);
             cgp *= x.c * x.g;
             qbar += x.w;
         }
@@ -189,20 +203,23 @@ __device__ inline RevOut reaction_vjp(const DevMech& m, const RxnRec& r,
     return o;
 }
 
-// one DPP move of a double (both halves with the same control)
+// one DPP move of a double (both halves with the same control); lanes of
+// rows outside ROW_MASK receive unspecified values
 template <int CTRL, int ROW_MASK>
 __device__ inline double dpp(double v) {
     const int2 h = __builtin_bit_cast(int2, v);
     int2 r;
-    r.x = __builtin_amdgcn_update_dpp(0, h.x, CTRL, ROW_MASK, 0xf, false);
-    r.y = __builtin_amdgcn_update_dpp(0, h.y, CTRL, ROW_MASK, 0xf, false);
+    r.x = __builtin_amdgcn_mov_dpp(h.x, CTRL, ROW_MASK, 0xf, false);
+    r.y = __builtin_amdgcn_mov_dpp(h.y, CTRL, ROW_MASK, 0xf, false);
     return __builtin_bit_cast(double, r);
 }
 
 // Sum over the 64 lanes with DPP row operations (no LDS traffic), in a fixed
-// order; the total lands in lane 63.  Quads, half rows and rows are summed
-// with quad permutations and mirrors; row 15's total is broadcast into rows
-// 1 and 3, then lane 31's into rows 2 and 3.
+// order; the total lands in lane 63 (other lanes end with partial or
+// unspecified values).  Quads, half rows and rows are summed with quad
+// permutations and mirrors, after which every lane holds its row's sum; row
+// 2's sum is added into row 3 (and row 0's into row 1) by the broadcast of
+// lane 15 of the row below, then lane 31's value (rows 0 + 1) into row 3.
 __device__ inline double wave_sum(double v) {
     v += dpp<0xb1, 0xf>(v);    // quad_perm [1, 0, 3, 2]
     v += dpp<0x4e, 0xf>(v);    // quad_perm [2, 3, 0, 1]
@@ -354,40 +371,39 @@ __global__ __launch_bounds__(kVjpWaves * 64) void vjp_kernel(
 #pragma unroll
             for (int i = 0; i < MAXOWN; ++i) {
                 if (i < nown) {
-                    // two entries per step, their loads issued together
+                    // two entries (four words) per step, their loads issued
+                    // together; the coefficients are scalar doubles
                     double sc0 = cc[i], sg0 = gam[i], sc1 = 0.0, sg1 = 0.0;
                     double sw0 = ws[i], sw1 = 0.0;
                     int e = bound[i];
-                    for (; e + 1 < bound[i + 1]; e += 2) {
-                        const uint32_t g0 = gent[e], g1 = gent[e + 1];
-                        const int o0 = int(g0 & 0xffffu) + lane * 8, o1 = int(g1 & 0xffffu) + lane * 8;
+                    for (; e + 4 <= bound[i + 1]; e += 4) {
+                        const GatherCoef g0 = gather_coef(gent[e], gent[e + 1]);
+                        const GatherCoef g1 = gather_coef(gent[e + 2], gent[e + 3]);
+                        const int o0 = g0.off + lane * 8, o1 = g1.off + lane * 8;
                         const double a0 = *reinterpret_cast<const double*>(plane_a + o0);
                         const double b0 = *reinterpret_cast<const double*>(plane_b + o0);
                         const double a1 = *reinterpret_cast<const double*>(plane_a + o1);
                         const double b1 = *reinterpret_cast<const double*>(plane_b + o1);
-                        const double f0 = double((g0 >> 16) & 0xffu), r0 = double(g0 >> 24);
-                        const double f1 = double((g1 >> 16) & 0xffu), r1 = double(g1 >> 24);
-                        sc0 = fma(f0, a0, fma(-r0, b0, sc0));
-                        sg0 = fma(f0 - r0, b0, sg0);
-                        sc1 = fma(f1, a1, fma(-r1, b1, sc1));
-                        sg1 = fma(f1 - r1, b1, sg1);
+                        sc0 = fma(g0.nf, a0, fma(g0.mnr, b0, sc0));
+                        sg0 = fma(g0.d, b0, sg0);
+                        sc1 = fma(g1.nf, a1, fma(g1.mnr, b1, sc1));
+                        sg1 = fma(g1.d, b1, sg1);
                         if (WITH_W) {
                             const double q0 = *reinterpret_cast<const double*>(plane_q + o0);
                             const double q1 = *reinterpret_cast<const double*>(plane_q + o1);
-                            sw0 = fma(r0 - f0, q0, sw0);
-                            sw1 = fma(r1 - f1, q1, sw1);
+                            sw0 = fma(-g0.d, q0, sw0);
+                            sw1 = fma(-g1.d, q1, sw1);
                         }
                     }
                     if (e < bound[i + 1]) {
-                        const uint32_t g = gent[e];
-                        const int off = int(g & 0xffffu) + lane * 8;
+                        const GatherCoef g = gather_coef(gent[e], gent[e + 1]);
+                        const int off = g.off + lane * 8;
                         const double av = *reinterpret_cast<const double*>(plane_a + off);
                         const double bv = *reinterpret_cast<const double*>(plane_b + off);
-                        const double nf = double((g >> 16) & 0xffu), nr = double(g >> 24);
-                        sc0 = fma(nf, av, fma(-nr, bv, sc0));
-                        sg0 = fma(nf - nr, bv, sg0);
+                        sc0 = fma(g.nf, av, fma(g.mnr, bv, sc0));
+                        sg0 = fma(g.d, bv, sg0);
                         if (WITH_W)
-                            sw0 = fma(nr - nf, *reinterpret_cast<const double*>(plane_q + off), sw0);
+                            sw0 = fma(-g.d, *reinterpret_cast<const double*>(plane_q + off), sw0);
                     }
                     cc[i] = sc0 + sc1;
                     gam[i] = sg0 + sg1;

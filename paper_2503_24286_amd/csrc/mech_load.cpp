@@ -200,7 +200,9 @@ struct HostSched {
     std::vector<int> slot_of, chunk_of;
 };
 
-int build_schedule(const SchedInput& in, int waves, int rpw, int own_cap,
+// row_bytes: the kernel's LDS bytes per species row; participants' offsets
+// in the reaction records are species * row_bytes
+int build_schedule(const SchedInput& in, int waves, int rpw, int own_cap, int row_bytes,
                    const std::vector<std::vector<int>>& gathered, HostSched& out) {
     const int S = in.S, R = in.R;
     const auto& rtype = *in.rtype;
@@ -288,7 +290,6 @@ int build_schedule(const SchedInput& in, int waves, int rpw, int own_cap,
     out.slot_of.assign(R, -1);
     out.chunk_of.assign(R, -1);
     out.pd_of_wave.assign(waves, {});
-    const int cg_stride = kTile * 16;  // bytes per species row of the C/G tile
     for (int c = 0; c < out.n_chunks; ++c) {
         std::vector<double> wl(waves, 0.0);
         std::vector<int> used(waves, 0);
@@ -313,8 +314,8 @@ int build_schedule(const SchedInput& in, int waves, int rpw, int own_cap,
             r.nr = int(rj.size());
             r.np = int(pj.size());
             for (int s = 0; s < kMaxSide; ++s) {
-                r.r[s] = s < r.nr ? rj[s] * cg_stride : 0;
-                r.p[s] = s < r.np ? pj[s] * cg_stride : 0;
+                r.r[s] = s < r.nr ? rj[s] * row_bytes : 0;
+                r.p[s] = s < r.np ? pj[s] * row_bytes : 0;
             }
             r.dnu = (*in.dnu)[j];
             r.prow = j;
@@ -452,12 +453,12 @@ int load_mechanism(const char* path, pyro_mech** out) {
         for (auto& e : part[k]) g_part[e[0]].push_back(k);
     }
     HostSched fw, bw;
-    if (int rc = build_schedule(sin, kWaves, kRxnPerWave, kMaxOwn, g_net, fw)) {
+    if (int rc = build_schedule(sin, kWaves, kRxnPerWave, kMaxOwn, kTile * 16, g_net, fw)) {
         delete m;
         return rc;
     }
     if (int rc = build_schedule(sin, kVjpWaves, 1, std::max(4, (S + kVjpWaves - 1) / kVjpWaves),
-                                g_part, bw)) {
+                                kVjpRow, g_part, bw)) {
         delete m;
         return rc;
     }
@@ -470,23 +471,31 @@ int load_mechanism(const char* path, pyro_mech** out) {
     // forward gathering lists: (chunk, wave, owned species) -> (slot, nu).
     // gptr holds, per (chunk, wave), kMaxOwn + 1 boundaries: the entries of
     // owned species i span [gptr[base + i], gptr[base + i + 1]).
+    auto top16 = [](double x) {
+        uint64_t b;
+        std::memcpy(&b, &x, sizeof b);
+        return uint32_t(b >> 48);
+    };
     std::vector<int32_t> gptr;
     std::vector<GatherEntry> gent;
     gather_lists(fw, [&](int k, int c, std::vector<uint32_t>& out) {
         for (auto& e : by_species[k])
             if (fw.chunk_of[e.first] == c) {
                 const uint32_t qoff = uint32_t(fw.slot_of[e.first] * kTile * 8);
-                out.push_back(qoff | (uint32_t(uint16_t(int16_t(int(e.second)))) << 16));
+                out.push_back(qoff | (top16(double(e.second)) << 16));
             }
     }, gptr, gent);
-    // reverse-sweep gathering lists: per participant (slot, nu', nu'')
+    // reverse-sweep gathering lists: per participant two words holding the
+    // slot and the coefficients nu', -nu'', nu' - nu'' as the upper 16 bits
+    // of their doubles; boundaries count words
     std::vector<int32_t> vgptr;
     std::vector<uint32_t> vgent;
     gather_lists(bw, [&](int k, int c, std::vector<uint32_t>& out) {
         for (auto& e : part[k])
-            if (bw.chunk_of[e[0]] == c)
-                out.push_back(uint32_t(bw.slot_of[e[0]] * kTile * 8) | (uint32_t(e[1]) << 16) |
-                              (uint32_t(e[2]) << 24));
+            if (bw.chunk_of[e[0]] == c) {
+                out.push_back(uint32_t(bw.slot_of[e[0]] * kTile * 8) | (top16(double(e[1])) << 16));
+                out.push_back(top16(-double(e[2])) | (top16(double(e[1] - e[2])) << 16));
+            }
     }, vgptr, vgent);
     std::vector<double> comp_d(f.comp.begin(), f.comp.end());
     if (comp_d.empty()) comp_d.push_back(0.0);

@@ -35,6 +35,7 @@ constexpr int kMaxSide = 3;
 // Max distinct T_mid values among the species (Newton kernel groups).
 constexpr int kMaxTmidGroups = 4;
 constexpr int kVjpWaves = 16;            // wavefronts of the reverse-sweep workgroup
+constexpr int kVjpRow = kTile * 24;       // bytes per species row of the reverse sweep: C, G, wbar
 
 // Reaction classes.
 enum : int32_t { kElementary = 0, kThirdBody = 1, kLindemann = 2, kTroe = 3,
@@ -78,8 +79,8 @@ struct FalloffRec {
 static_assert(sizeof(FalloffRec) == 64, "FalloffRec must be 64 bytes");
 
 // Gathering entry: the byte offset of a rate-of-progress slot in its chunk
-// buffer (bits 0-15) and the net coefficient nu as a signed 16-bit integer
-// (bits 16-31).
+// buffer (bits 0-15) and the upper 16 bits of the double holding the net
+// coefficient nu (bits 16-31; exact for integers up to 31 in magnitude).
 using GatherEntry = uint32_t;
 
 // Newton-kernel data: NASA7 coefficients a1..a6 of each range and 1/W.
@@ -111,6 +112,13 @@ __device__ inline cptr<T> cst(const T* p) {
     return (cptr<T>)(p);
 }
 
+// The double whose upper 16 bits are top (lower 48 bits zero).  Table
+// coefficients stored this way reach the FMAs as scalar operands, with no
+// conversion instruction.
+__device__ inline double from_top16(uint32_t top) {
+    return __builtin_bit_cast(double, uint64_t(top) << 48);
+}
+
 // The tables of one work schedule (see the loader): chunks of waves x rpw
 // reaction slots, species owned per wave, gathering lists.
 struct DevSched {
@@ -122,7 +130,10 @@ struct DevSched {
     const int32_t* own;                  // [waves][kMaxOwn]
     const int32_t* n_own;                // [waves]
     const int32_t* gptr;                 // [n_chunks][waves][kMaxOwn + 1]
-    const uint32_t* gent;                // reverse sweep: slot offset | nu' << 16 | nu'' << 24
+    // reverse sweep: two words per entry, (slot offset | top16(nu') << 16,
+    // top16(-nu'') | top16(nu' - nu'') << 16), top16(x) being the upper 16
+    // bits of the double x (exact for small integers)
+    const uint32_t* gent;
     const int32_t* pd_list;              // [waves][kMaxPd] third-body rows in chunk order
 };
 
