@@ -332,12 +332,12 @@ __global__ __launch_bounds__(kWaves * 64) void wdot_f64_kernel(
                     const GatherEntry g1 = m.gent[e + 1];
                     const double q0 = *reinterpret_cast<const double*>(qb + (g0 & 0xffffu) + lane * 8);
                     const double q1 = *reinterpret_cast<const double*>(qb + (g1 & 0xffffu) + lane * 8);
-                    a = fma(from_top16(g0 >> 16), q0, a);
-                    b = fma(from_top16(g1 >> 16), q1, b);
+                    a = fma(double(int16_t(g0 >> 16)), q0, a);
+                    b = fma(double(int16_t(g1 >> 16)), q1, b);
                 }
                 if (e < e1) {
                     const GatherEntry g0 = m.gent[e];
-                    a = fma(from_top16(g0 >> 16),
+                    a = fma(double(int16_t(g0 >> 16)),
                             *reinterpret_cast<const double*>(qb + (g0 & 0xffffu) + lane * 8), a);
                 }
                 acc[i] = a + b;

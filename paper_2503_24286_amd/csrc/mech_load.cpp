@@ -482,7 +482,7 @@ int load_mechanism(const char* path, pyro_mech** out) {
         for (auto& e : by_species[k])
             if (fw.chunk_of[e.first] == c) {
                 const uint32_t qoff = uint32_t(fw.slot_of[e.first] * kTile * 8);
-                out.push_back(qoff | (top16(double(e.second)) << 16));
+                out.push_back(qoff | (uint32_t(uint16_t(int16_t(int(e.second)))) << 16));
             }
     }, gptr, gent);
     // reverse-sweep gathering lists: per participant two words holding the

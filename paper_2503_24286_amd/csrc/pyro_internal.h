@@ -79,8 +79,8 @@ struct FalloffRec {
 static_assert(sizeof(FalloffRec) == 64, "FalloffRec must be 64 bytes");
 
 // Gathering entry: the byte offset of a rate-of-progress slot in its chunk
-// buffer (bits 0-15) and the upper 16 bits of the double holding the net
-// coefficient nu (bits 16-31; exact for integers up to 31 in magnitude).
+// buffer (bits 0-15) and the net coefficient nu as a signed 16-bit integer
+// (bits 16-31).
 using GatherEntry = uint32_t;
 
 // Newton-kernel data: NASA7 coefficients a1..a6 of each range and 1/W.
