@@ -19,6 +19,7 @@
 #include <algorithm>
 #include <array>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <fstream>
 #include <numeric>
@@ -617,6 +618,7 @@ int load_mechanism(const char* path, pyro_mech** out) {
         {vpd_list.data(), vpd_list.size() * sizeof(int32_t), 0},
         {rxn_kc.data(), rxn_kc.size() * sizeof(double), 0},
         {eps_frag.data(), eps_frag.size() * sizeof(double), 0},
+        {f.eff.data(), f.eff.size() * sizeof(double), 0},
     };
     size_t total = 0;
     for (auto& p : parts) {
@@ -624,7 +626,8 @@ int load_mechanism(const char* path, pyro_mech** out) {
         total = align256(total + p.bytes);
     }
     std::vector<uint8_t> host(total, 0);
-    for (auto& p : parts) std::memcpy(host.data() + p.off, p.src, p.bytes);
+    for (auto& p : parts)
+        if (p.bytes) std::memcpy(host.data() + p.off, p.src, p.bytes);
 
     hipError_t err = hipGetDevice(&m->device);
     if (err != hipSuccess) {
@@ -684,6 +687,13 @@ int load_mechanism(const char* path, pyro_mech** out) {
     v.pd_list = reinterpret_cast<const int32_t*>(base + parts[21].off);
     d.rxn_kc = reinterpret_cast<const double*>(base + parts[22].off);
     d.eps_frag = reinterpret_cast<const double*>(base + parts[23].off);
+    v.eff = reinterpret_cast<const double*>(base + parts[24].off);
+    // the reverse sweep keeps the efficiencies in LDS when they fit beside its
+    // tile (PYRO_VJP_SCALAR_EFFICIENCIES=1 keeps them in the scalar tables)
+    const char* scalar_eff = std::getenv("PYRO_VJP_SCALAR_EFFICIENCIES");
+    m->vjp_eps_lds = n_pd > 0 && vjp_lds_bytes_for(m, true) <= size_t(160 * 1024) &&
+                     !(scalar_eff && scalar_eff[0] == '1');
+    v.eps_lds = m->vjp_eps_lds ? 1 : 0;
     err = prepare_production_rates(m);
     if (err == hipSuccess) err = prepare_vjp(m);
     if (err != hipSuccess) {
