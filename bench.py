@@ -413,12 +413,15 @@ def main():
     wdot_ms = _time_ms(lambda: pyro.production_rates(gm, rho, T_out, Y_d, out=w2),
                        max(args.steps, 3), stream)
     # the same with each alternative kernel variant (equilibrium constants per
-    # reaction; third-body concentrations on the FP64 matrix cores)
+    # reaction; third-body concentrations, net rates nu q on the FP64 matrix cores)
     from paper_2503_24286_amd import _lib
     variant_ms = {}
     default_variant = gm.wdot_variant
     for name, v in (("reaction_equilibrium", _lib.PYRO_WDOT_REACTION_EQUILIBRIUM),
                     ("third_body_on_mfma", default_variant | _lib.PYRO_WDOT_MFMA_THIRD_BODY),
+                    ("net_rates_on_mfma", default_variant | _lib.PYRO_WDOT_MFMA_NET_RATES),
+                    ("third_body_and_net_rates_on_mfma", default_variant
+                     | _lib.PYRO_WDOT_MFMA_THIRD_BODY | _lib.PYRO_WDOT_MFMA_NET_RATES),
                     ("reaction_equilibrium_third_body_on_mfma",
                      _lib.PYRO_WDOT_REACTION_EQUILIBRIUM | _lib.PYRO_WDOT_MFMA_THIRD_BODY)):
         gm.wdot_variant = v

@@ -76,7 +76,13 @@ enum pyro_wdot_variant {
      * [M]_j = sum_k eps_jk C_k (a dense contraction) of a 64-cell tile on the
      * FP64 matrix cores (v_mfma_f64_16x16x4f64) instead of per-wave FMA
      * passes; [M] is then held in LDS (512 B per third-body reaction) */
-    PYRO_WDOT_MFMA_THIRD_BODY = 2
+    PYRO_WDOT_MFMA_THIRD_BODY = 2,
+    /* flag, combinable with the others: the net production rates
+     * omega = nu q (eq. production_rates) of a 64-cell tile accumulated on
+     * the FP64 matrix cores over the reaction chunks with the dense nu
+     * (v_mfma_f64_16x16x4f64), instead of the sparse per-species gathering;
+     * at most 64 species */
+    PYRO_WDOT_MFMA_NET_RATES = 4
 };
 
 typedef struct pyro_mech pyro_mech;
@@ -115,7 +121,8 @@ PYRO_API int pyro_mech_load(const char* path, pyro_mech** out);
 PYRO_API void pyro_mech_free(pyro_mech* mech);
 PYRO_API int pyro_mech_get_info(const pyro_mech* mech, pyro_mech_info* info);
 /* Selects the production-rate kernel variant (enum pyro_wdot_variant, an
- * equilibrium variant optionally or-ed with PYRO_WDOT_MFMA_THIRD_BODY) used by
+ * equilibrium variant optionally or-ed with PYRO_WDOT_MFMA_THIRD_BODY and
+ * PYRO_WDOT_MFMA_NET_RATES) used by
  * pyro_production_rates and the surrogate's fallback.  The loader picks the
  * species variant when its LDS tile fits and the reaction variant otherwise;
  * PYRO_E_UNSUPPORTED if the requested variant cannot run this mechanism.

@@ -24,6 +24,7 @@ PYRO_F32 = 1
 PYRO_WDOT_SPECIES_EQUILIBRIUM = 0
 PYRO_WDOT_REACTION_EQUILIBRIUM = 1
 PYRO_WDOT_MFMA_THIRD_BODY = 2
+PYRO_WDOT_MFMA_NET_RATES = 4
 
 
 class PyroError(RuntimeError):

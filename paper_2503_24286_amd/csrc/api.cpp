@@ -96,12 +96,16 @@ int pyro_mech_get_info(const pyro_mech* m, pyro_mech_info* info) {
 int pyro_mech_set_wdot_variant(pyro_mech* m, int variant) {
     clear_error();
     if (!m) return fail(PYRO_E_ARG, "null mechanism handle");
-    if (variant < 0 || variant > (PYRO_WDOT_REACTION_EQUILIBRIUM | PYRO_WDOT_MFMA_THIRD_BODY))
+    if (variant < 0 || variant > (PYRO_WDOT_REACTION_EQUILIBRIUM | PYRO_WDOT_MFMA_THIRD_BODY |
+                                  PYRO_WDOT_MFMA_NET_RATES))
         return fail(PYRO_E_ARG, "unknown production-rate variant");
     const bool rkc = variant & PYRO_WDOT_REACTION_EQUILIBRIUM;
     const bool mm = variant & PYRO_WDOT_MFMA_THIRD_BODY;
+    const bool nq = variant & PYRO_WDOT_MFMA_NET_RATES;
     if (rkc && !m->kc_ok)
         return fail(PYRO_E_UNSUPPORTED, "reactions mix species with different NASA7 T_mid");
+    if (nq && !nq_supported(m))
+        return fail(PYRO_E_UNSUPPORTED, "the matrix-core net rates need at most 64 species");
     if (production_rates_lds_bytes(m, rkc, mm) > 160 * 1024)
         return fail(PYRO_E_UNSUPPORTED, rkc ? "mechanism too large for the LDS tile"
                                             : "species rows of this mechanism exceed the LDS tile");

@@ -191,7 +191,7 @@ __device__ inline double rate_of_progress(const DevMech& m, const RxnRec& r,
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-template <int MAXOWN, int MAXPD, bool RKC, bool MM>
+template <int MAXOWN, int MAXPD, bool RKC, bool MM, bool NQ>
 __global__ __launch_bounds__(kWaves * 64) void wdot_f64_kernel(
     DevMech m, int64_t n, int64_t ld, const double* __restrict__ rho,
     const double* __restrict__ T, const double* __restrict__ Y,
@@ -286,12 +286,27 @@ __global__ __launch_bounds__(kWaves * 64) void wdot_f64_kernel(
     }
 
     // ---- reaction chunks and gathering
-    double acc[MAXOWN];
+    double acc[NQ ? 1 : MAXOWN];
 #pragma unroll
-    for (int i = 0; i < MAXOWN; ++i) acc[i] = 0.0;
+    for (int i = 0; i < (NQ ? 1 : MAXOWN); ++i) acc[i] = 0.0;
+    // NQ: omega[64 cells x S] accumulated on the matrix cores over the chunks,
+    // omega += q[cells x 16 slots] nu[16 slots x S]; wave w holds the
+    // 16-cell x 16-species output blocks (cell block w & 3, species blocks
+    // (w >> 2) and (w >> 2) + 2)
+    const int nq_cb = w & 3, nq_sb = w >> 2;
+    d4 wacc[2] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
     static_assert(kRxnPerWave == 2, "the reaction phase handles reactions in pairs");
     for (int ch = 0; ch < m.n_chunks; ++ch) {
         unsigned char* qb = qbase + (ch & 1) * kQBuf;
+        // NQ: this chunk's B fragments of nu, loaded before the rates are evaluated
+        double nub[2][4];
+        if constexpr (NQ) {
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int kk = 0; kk < 4; ++kk)
+                    nub[b][kk] = m.nu_frag[((size_t(ch) * 4 + nq_sb + 2 * b) * 4 + kk) * 64 + lane];
+        }
         const RxnRec* rb = m.rxn + (size_t(ch) * kWaves + w) * kRxnPerWave;
         const RxnRec r0 = rb[0];
         const RxnRec r1 = rb[1];
@@ -311,10 +326,26 @@ __global__ __launch_bounds__(kWaves * 64) void wdot_f64_kernel(
         if (r0.cls != kNoReaction)
             *reinterpret_cast<double*>(qb + r0.qoff + lane * 8) = rate_of_progress<RKC>(
                 m, r0, params, lds, lane, kf0, M0, Tc, lnT, invT, invRT, rtp, irtp, kc);
+        else if (NQ)   // empty slots enter the dense product: zero, not stale LDS
+            *reinterpret_cast<double*>(qb + (2 * w) * kTile * 8 + lane * 8) = 0.0;
         if (r1.cls != kNoReaction)
             *reinterpret_cast<double*>(qb + r1.qoff + lane * 8) = rate_of_progress<RKC>(
                 m, r1, params, lds, lane, kf1, M1, Tc, lnT, invT, invRT, rtp, irtp, kc + 16);
+        else if (NQ)
+            *reinterpret_cast<double*>(qb + (2 * w + 1) * kTile * 8 + lane * 8) = 0.0;
         __syncthreads();
+        if constexpr (NQ) {
+            // A[cell][slot]: slot 4 kk + l/16, cell 16 cb + l%16 of the chunk buffer
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) {
+                const double a = reinterpret_cast<const double*>(
+                    qb + (4 * kk + (lane >> 4)) * kTile * 8)[16 * nq_cb + (lane & 15)];
+#pragma unroll
+                for (int b = 0; b < 2; ++b)
+                    wacc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, nub[b][kk], wacc[b], 0, 0, 0);
+            }
+            continue;
+        }
         // gather: the boundaries of all owned species in one scalar load,
         // then each species' entries in pairs
         const int32_t* gp = m.gptr + (size_t(ch) * kWaves + w) * (kMaxOwn + 1);
@@ -344,65 +375,81 @@ __global__ __launch_bounds__(kWaves * 64) void wdot_f64_kernel(
             }
         }
     }
-    if (valid) {
+    if constexpr (NQ) {
+        // D: register i of lane l is cell 4 i + l/16, species l % 16 of the block
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            const int k = 16 * (nq_sb + 2 * b) + (lane & 15);
+            if (k < m.S) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int64_t ci = int64_t(blockIdx.x) * kTile + 16 * nq_cb + 4 * i + (lane >> 4);
+                    if (ci < n) wdot[size_t(k) * ld + ci] = wacc[b][i];
+                }
+            }
+        }
+    } else if (valid) {
 #pragma unroll
         for (int i = 0; i < MAXOWN; ++i)
             if (i < nown) wdot[size_t(own[i]) * ld + cell] = acc[i];
     }
 }
 
-template <int MAXOWN, int MAXPD, bool RKC, bool MM>
+template <int MAXOWN, int MAXPD, bool RKC, bool MM, bool NQ>
 hipError_t launch_f64(const pyro_mech* m, int64_t n, int64_t ld, const double* rho,
                       const double* T, const double* Y, double* wdot,
                       const double* params, hipStream_t stream, const int64_t* n_dev) {
     const size_t lds = production_rates_lds_bytes(m, RKC, MM);
     const int64_t blocks = (n + kTile - 1) / kTile;
-    hipLaunchKernelGGL((wdot_f64_kernel<MAXOWN, MAXPD, RKC, MM>), dim3(unsigned(blocks)),
+    hipLaunchKernelGGL((wdot_f64_kernel<MAXOWN, MAXPD, RKC, MM, NQ>), dim3(unsigned(blocks)),
                        dim3(kWaves * 64), lds, stream, m->dev, n, ld, rho, T, Y, wdot,
                        params ? params : m->dev.params, n_dev);
     return hipGetLastError();
 }
 
 // Kernel instances: (species owned per wave, [M] slots per wave, variant).
-template <int MAXOWN, int MAXPD, bool RKC, bool MM>
+template <int MAXOWN, int MAXPD, bool RKC, bool MM, bool NQ>
 hipError_t set_lds(int bytes) {
     return hipFuncSetAttribute(
-        reinterpret_cast<const void*>(&wdot_f64_kernel<MAXOWN, MAXPD, RKC, MM>),
+        reinterpret_cast<const void*>(&wdot_f64_kernel<MAXOWN, MAXPD, RKC, MM, NQ>),
         hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
-template <int MAXPD, bool RKC, bool MM>
+// the NQ instances exist for at most 16 species per wave (NQ needs S <= 64)
+template <int MAXPD, bool RKC, bool MM, bool NQ>
 hipError_t dispatch_own(const pyro_mech* m, int64_t n, int64_t ld, const double* r,
                         const double* t, const double* y, double* o, const double* params,
                         hipStream_t stream, const int64_t* nd) {
-    if (m->max_own <= 8) return launch_f64<8, MAXPD, RKC, MM>(m, n, ld, r, t, y, o, params, stream, nd);
-    if (m->max_own <= 16) return launch_f64<16, MAXPD, RKC, MM>(m, n, ld, r, t, y, o, params, stream, nd);
-    if (m->max_own <= 32) return launch_f64<32, MAXPD, RKC, MM>(m, n, ld, r, t, y, o, params, stream, nd);
-    return launch_f64<64, MAXPD, RKC, MM>(m, n, ld, r, t, y, o, params, stream, nd);
+    if (m->max_own <= 8) return launch_f64<8, MAXPD, RKC, MM, NQ>(m, n, ld, r, t, y, o, params, stream, nd);
+    if (NQ || m->max_own <= 16)
+        return launch_f64<16, MAXPD, RKC, MM, NQ>(m, n, ld, r, t, y, o, params, stream, nd);
+    if (m->max_own <= 32) return launch_f64<32, MAXPD, RKC, MM, false>(m, n, ld, r, t, y, o, params, stream, nd);
+    return launch_f64<64, MAXPD, RKC, MM, false>(m, n, ld, r, t, y, o, params, stream, nd);
 }
 
-template <bool RKC, bool MM>
+template <bool RKC, bool MM, bool NQ>
 hipError_t set_lds_variant(int bytes) {
     hipError_t e = hipSuccess;
-    // the MFMA variant holds no per-wave [M] slots: one MAXPD instance
+    // the MFMA third-body variant holds no per-wave [M] slots: one MAXPD instance
     const hipError_t all[] = {
-        set_lds<8, 8, RKC, MM>(bytes),  set_lds<16, 8, RKC, MM>(bytes),
-        set_lds<32, 8, RKC, MM>(bytes), set_lds<64, 8, RKC, MM>(bytes),
-        MM ? hipSuccess : set_lds<8, 16, RKC, MM>(bytes),
-        MM ? hipSuccess : set_lds<16, 16, RKC, MM>(bytes),
-        MM ? hipSuccess : set_lds<32, 16, RKC, MM>(bytes),
-        MM ? hipSuccess : set_lds<64, 16, RKC, MM>(bytes)};
+        set_lds<8, 8, RKC, MM, NQ>(bytes),  set_lds<16, 8, RKC, MM, NQ>(bytes),
+        NQ ? hipSuccess : set_lds<32, 8, RKC, MM, false>(bytes),
+        NQ ? hipSuccess : set_lds<64, 8, RKC, MM, false>(bytes),
+        MM ? hipSuccess : set_lds<8, 16, RKC, MM, NQ>(bytes),
+        MM ? hipSuccess : set_lds<16, 16, RKC, MM, NQ>(bytes),
+        MM || NQ ? hipSuccess : set_lds<32, 16, RKC, MM, false>(bytes),
+        MM || NQ ? hipSuccess : set_lds<64, 16, RKC, MM, false>(bytes)};
     for (hipError_t x : all)
         if (x != hipSuccess) e = x;
     return e;
 }
 
-template <bool RKC, bool MM>
+template <bool RKC, bool MM, bool NQ>
 hipError_t dispatch_variant(const pyro_mech* m, int64_t n, int64_t ld, const double* r,
                             const double* t, const double* y, double* o, const double* params,
                             hipStream_t stream, const int64_t* nd) {
-    if (MM || m->max_pdw <= 8) return dispatch_own<8, RKC, MM>(m, n, ld, r, t, y, o, params, stream, nd);
-    return dispatch_own<16, RKC, MM>(m, n, ld, r, t, y, o, params, stream, nd);
+    if (MM || m->max_pdw <= 8) return dispatch_own<8, RKC, MM, NQ>(m, n, ld, r, t, y, o, params, stream, nd);
+    return dispatch_own<16, RKC, MM, NQ>(m, n, ld, r, t, y, o, params, stream, nd);
 }
 
 }  // namespace
@@ -415,21 +462,27 @@ size_t production_rates_lds_bytes(const pyro_mech* m, bool reaction_equilibrium,
 
 hipError_t prepare_production_rates(const pyro_mech* m) {
     hipError_t e = hipSuccess;
-    for (const int v : {0, 1, 2, 3}) {
-        const bool rkc = v & 1, mm = v & 2;
+    for (const int v : {0, 1, 2, 3, 4, 5, 6, 7}) {
+        const bool rkc = v & 1, mm = v & 2, nq = v & 4;
         const size_t bytes = production_rates_lds_bytes(m, rkc, mm);
-        if (bytes > 160 * 1024 || (rkc && !m->kc_ok)) continue;
+        if (bytes > 160 * 1024 || (rkc && !m->kc_ok) || (nq && !nq_supported(m))) continue;
         hipError_t x;
         switch (v) {
-            case 0: x = set_lds_variant<false, false>(int(bytes)); break;
-            case 1: x = set_lds_variant<true, false>(int(bytes)); break;
-            case 2: x = set_lds_variant<false, true>(int(bytes)); break;
-            default: x = set_lds_variant<true, true>(int(bytes));
+            case 0: x = set_lds_variant<false, false, false>(int(bytes)); break;
+            case 1: x = set_lds_variant<true, false, false>(int(bytes)); break;
+            case 2: x = set_lds_variant<false, true, false>(int(bytes)); break;
+            case 3: x = set_lds_variant<true, true, false>(int(bytes)); break;
+            case 4: x = set_lds_variant<false, false, true>(int(bytes)); break;
+            case 5: x = set_lds_variant<true, false, true>(int(bytes)); break;
+            case 6: x = set_lds_variant<false, true, true>(int(bytes)); break;
+            default: x = set_lds_variant<true, true, true>(int(bytes));
         }
         if (x != hipSuccess) e = x;
     }
     return e;
 }
+
+bool nq_supported(const pyro_mech* m) { return m->S <= 64 && m->max_own <= 16; }
 
 hipError_t launch_production_rates(const pyro_mech* m, int64_t n, int64_t ld, int dtype,
                                    const void* rho, const void* T, const void* Y,
@@ -441,14 +494,14 @@ hipError_t launch_production_rates(const pyro_mech* m, int64_t n, int64_t ld, in
     const double* y = static_cast<const double*>(Y);
     double* o = static_cast<double*>(wdot);
     switch (m->wdot_variant) {
-        case PYRO_WDOT_REACTION_EQUILIBRIUM:
-            return dispatch_variant<true, false>(m, n, ld, r, t, y, o, params, stream, n_dev);
-        case PYRO_WDOT_MFMA_THIRD_BODY:
-            return dispatch_variant<false, true>(m, n, ld, r, t, y, o, params, stream, n_dev);
-        case PYRO_WDOT_REACTION_EQUILIBRIUM | PYRO_WDOT_MFMA_THIRD_BODY:
-            return dispatch_variant<true, true>(m, n, ld, r, t, y, o, params, stream, n_dev);
-        default:
-            return dispatch_variant<false, false>(m, n, ld, r, t, y, o, params, stream, n_dev);
+        case 1: return dispatch_variant<true, false, false>(m, n, ld, r, t, y, o, params, stream, n_dev);
+        case 2: return dispatch_variant<false, true, false>(m, n, ld, r, t, y, o, params, stream, n_dev);
+        case 3: return dispatch_variant<true, true, false>(m, n, ld, r, t, y, o, params, stream, n_dev);
+        case 4: return dispatch_variant<false, false, true>(m, n, ld, r, t, y, o, params, stream, n_dev);
+        case 5: return dispatch_variant<true, false, true>(m, n, ld, r, t, y, o, params, stream, n_dev);
+        case 6: return dispatch_variant<false, true, true>(m, n, ld, r, t, y, o, params, stream, n_dev);
+        case 7: return dispatch_variant<true, true, true>(m, n, ld, r, t, y, o, params, stream, n_dev);
+        default: return dispatch_variant<false, false, false>(m, n, ld, r, t, y, o, params, stream, n_dev);
     }
 }
 

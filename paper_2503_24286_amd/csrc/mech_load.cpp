@@ -591,6 +591,25 @@ int load_mechanism(const char* path, pyro_mech** out) {
         }
     }
 
+    // B fragments of the net coefficients per forward chunk (S <= 64)
+    std::vector<double> nu_frag(S <= 64 ? size_t(std::max(n_chunks, 1)) * 4 * 4 * 64 : 1, 0.0);
+    if (S <= 64)
+        for (int c = 0; c < n_chunks; ++c)
+            for (int slot = 0; slot < kChunk; ++slot) {
+                const RxnRec& r = recs[size_t(c) * kChunk + slot];
+                if (r.cls == kNoReaction) continue;
+                const int j = r.prow;
+                std::vector<int> nu(S, 0);
+                for (int k : prod[j]) nu[k] += 1;
+                for (int k : reac[j]) nu[k] -= 1;
+                const int kk = slot / 4, row = slot % 4;
+                for (int k = 0; k < S; ++k) {
+                    if (!nu[k]) continue;
+                    const int sb = k / 16, l = row * 16 + k % 16;
+                    nu_frag[((size_t(c) * 4 + sb) * 4 + kk) * 64 + l] = double(nu[k]);
+                }
+            }
+
     // ---- one device allocation holding every table
     struct Part { const void* src; size_t bytes; size_t off; };
     std::vector<Part> parts = {
@@ -619,6 +638,7 @@ int load_mechanism(const char* path, pyro_mech** out) {
         {rxn_kc.data(), rxn_kc.size() * sizeof(double), 0},
         {eps_frag.data(), eps_frag.size() * sizeof(double), 0},
         {f.eff.data(), f.eff.size() * sizeof(double), 0},
+        {nu_frag.data(), nu_frag.size() * sizeof(double), 0},
     };
     size_t total = 0;
     for (auto& p : parts) {
@@ -688,6 +708,7 @@ int load_mechanism(const char* path, pyro_mech** out) {
     d.rxn_kc = reinterpret_cast<const double*>(base + parts[22].off);
     d.eps_frag = reinterpret_cast<const double*>(base + parts[23].off);
     v.eff = reinterpret_cast<const double*>(base + parts[24].off);
+    d.nu_frag = reinterpret_cast<const double*>(base + parts[25].off);
     // the reverse sweep keeps the efficiencies in LDS when they fit beside its
     // tile (PYRO_VJP_SCALAR_EFFICIENCIES=1 keeps them in the scalar tables)
     const char* scalar_eff = std::getenv("PYRO_VJP_SCALAR_EFFICIENCIES");

@@ -166,6 +166,10 @@ struct DevMech {
     // MFMA third-body variant: B fragments of eps^T, [pd block][K-step][lane]
     // = eps[16 pb + l%16][4 kk + l/16] (zero outside n_pd x S)
     const double* eps_frag;
+    // MFMA net-rate variant (S <= 64): B fragments of nu per chunk,
+    // [chunk][species block 0..3][K-step 0..3][lane] = nu[16 sb + l%16][reaction
+    // in slot 4 kk + l/16] (zero for empty slots and species past S)
+    const double* nu_frag;
     // surrogate
     int32_t E;                           // elements
     int32_t pad2;
@@ -233,6 +237,7 @@ hipError_t launch_production_rates_vjp(const pyro_mech* m, int64_t n, int64_t ld
                                        double* params_bar, double* wdot,
                                        const double* params, hipStream_t stream);
 size_t vjp_lds_bytes(const pyro_mech* m);
+bool nq_supported(const pyro_mech* m);
 size_t vjp_lds_bytes_for(const pyro_mech* m, bool eps_lds);
 hipError_t prepare_vjp(const pyro_mech* m);
 

@@ -150,8 +150,9 @@ def cfg3_mech():
 def test_both_equilibrium_variants_match_oracle(lib_mechs, cfg, n):
     """The species-equilibrium (per-species exp(g/RT) in LDS) and the
     reaction-equilibrium (combined coefficients, one exp per reversible
-    reaction) kernels, each with the third-body concentrations on the FMA
-    units or on the FP64 matrix cores, all pass the parity bar."""
+    reaction) kernels, each with the third-body concentrations and the net
+    rates nu q on the FMA units or on the FP64 matrix cores, all pass the
+    parity bar."""
     from paper_2503_24286_amd import _lib
     torch, pyro, gms = lib_mechs
     m = mechs.load_config(cfg)
@@ -159,9 +160,7 @@ def test_both_equilibrium_variants_match_oracle(lib_mechs, cfg, n):
     T, p, Y, rho = states(cfg, n, m.S, first=3333)
     before = gm.wdot_variant
     try:
-        for variant in (_lib.PYRO_WDOT_SPECIES_EQUILIBRIUM, _lib.PYRO_WDOT_REACTION_EQUILIBRIUM,
-                        _lib.PYRO_WDOT_SPECIES_EQUILIBRIUM | _lib.PYRO_WDOT_MFMA_THIRD_BODY,
-                        _lib.PYRO_WDOT_REACTION_EQUILIBRIUM | _lib.PYRO_WDOT_MFMA_THIRD_BODY):
+        for variant in range(8):   # equilibrium form | MFMA [M] | MFMA nu q
             gm.wdot_variant = variant
             assert gm.wdot_variant == variant
             announce(f"wdot variant {variant} cfg{cfg} n={n}")
@@ -199,8 +198,11 @@ def test_variant_selection_errors(cfg3_mech):
     with pytest.raises(_lib.PyroError) as e:
         gm.wdot_variant = _lib.PYRO_WDOT_SPECIES_EQUILIBRIUM
     assert e.value.code == _lib.PYRO_E_UNSUPPORTED
+    with pytest.raises(_lib.PyroError) as e:   # more than 64 species
+        gm.wdot_variant = _lib.PYRO_WDOT_REACTION_EQUILIBRIUM | _lib.PYRO_WDOT_MFMA_NET_RATES
+    assert e.value.code == _lib.PYRO_E_UNSUPPORTED
     with pytest.raises(_lib.PyroError) as e:
-        gm.wdot_variant = 7
+        gm.wdot_variant = 8
     assert e.value.code == _lib.PYRO_E_ARG
     with pytest.raises(_lib.PyroError) as e:
         gm.wdot_variant = -1
