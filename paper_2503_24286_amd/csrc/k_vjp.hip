@@ -451,36 +451,37 @@ __global__ __launch_bounds__(kVjpWaves * 64) void vjp_kernel(
                 if (p >= MAXPD - npdw) mbar[size_t(pl[p - (MAXPD - npdw)]) * kTile + lane] = Mr[p];
         }
         __syncthreads();
+        // ---- sum_j eps_jk Mbar_j for the wave's species: each Mbar row is
+        // read once for all of them, the efficiencies of a row (contiguous per
+        // wave) are scalar operands
+        double cmv[MAXOWN];
+#pragma unroll
+        for (int i = 0; i < MAXOWN; ++i) cmv[i] = 0.0;
+        {
+            const cptr<double> eo = cst(sc.effo) + size_t(w) * m.n_pd * MAXOWN;
+            int j = 0;
+            for (; j + 4 <= m.n_pd; j += 4) {
+                double mb[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) mb[u] = mbar[size_t(j + u) * kTile + lane];
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+#pragma unroll
+                    for (int i = 0; i < MAXOWN; ++i)
+                        cmv[i] = fma(eo[(j + u) * MAXOWN + i], mb[u], cmv[i]);
+            }
+            for (; j < m.n_pd; ++j) {
+                const double mb = mbar[size_t(j) * kTile + lane];
+#pragma unroll
+                for (int i = 0; i < MAXOWN; ++i) cmv[i] = fma(eo[j * MAXOWN + i], mb, cmv[i]);
+            }
+        }
         // ---- species results
 #pragma unroll
         for (int i = 0; i < MAXOWN; ++i) {
             if (i < nown) {
                 const int k = own[i];
-                double cm = 0.0;  // sum_j eps_jk Mbar_j
-                const cptr<double> et = cst(m.eff_t) + size_t(k) * (m.n_pd > 0 ? m.n_pd : 1);
-                if (sc.eps_lds) {
-                    double c1 = 0.0, c2 = 0.0, c3 = 0.0;
-                    int j = 0;
-                    for (; j + 4 <= m.n_pd; j += 4) {
-                        cm = fma(epsl[j * m.S + k], mbar[size_t(j) * kTile + lane], cm);
-                        c1 = fma(epsl[(j + 1) * m.S + k], mbar[size_t(j + 1) * kTile + lane], c1);
-                        c2 = fma(epsl[(j + 2) * m.S + k], mbar[size_t(j + 2) * kTile + lane], c2);
-                        c3 = fma(epsl[(j + 3) * m.S + k], mbar[size_t(j + 3) * kTile + lane], c3);
-                    }
-                    for (; j < m.n_pd; ++j) cm = fma(epsl[j * m.S + k], mbar[size_t(j) * kTile + lane], cm);
-                    cm += (c1 + c2) + c3;
-                } else {
-                    double c1 = 0.0, c2 = 0.0, c3 = 0.0;
-                    int j = 0;
-                    for (; j + 4 <= m.n_pd; j += 4) {
-                        cm = fma(et[j], mbar[size_t(j) * kTile + lane], cm);
-                        c1 = fma(et[j + 1], mbar[size_t(j + 1) * kTile + lane], c1);
-                        c2 = fma(et[j + 2], mbar[size_t(j + 2) * kTile + lane], c2);
-                        c3 = fma(et[j + 3], mbar[size_t(j + 3) * kTile + lane], c3);
-                    }
-                    for (; j < m.n_pd; ++j) cm = fma(et[j], mbar[size_t(j) * kTile + lane], cm);
-                    cm += (c1 + c2) + c3;
-                }
+                const double cm = cmv[i];  // sum_j eps_jk Mbar_j
                 // dL/dY_k = Cbar_k rho/W_k = (Cbar_k C_k) rho/(W_k C_k), with C_k
                 // still in this tile's LDS row (zero where Y_k <= 0)
                 const double ck = reinterpret_cast<const double*>(lds + k * kVRow)[lane];

@@ -558,6 +558,15 @@ int load_mechanism(const char* path, pyro_mech** out) {
     for (int w = 0; w < kVjpWaves; ++w)
         for (size_t i = 0; i < bw.pd_of_wave[w].size(); ++i)
             vpd_list[w * kMaxPd + i] = pd_row[bw.pd_of_wave[w][i]];
+    // the reverse sweep's efficiencies by (wave, third-body row, owned
+    // species): the MAXOWN values a wave needs for one row are contiguous
+    // (MAXOWN = the kernel instance's species-per-wave bound)
+    const int own_stride = bw.max_own <= 4 ? 4 : bw.max_own <= 8 ? 8 : 16;
+    std::vector<double> veffo(std::max(size_t(1), size_t(kVjpWaves) * n_pd * own_stride), 0.0);
+    for (int w = 0; w < kVjpWaves; ++w)
+        for (int j = 0; j < n_pd; ++j)
+            for (size_t i = 0; i < bw.own[w].size() && i < size_t(own_stride); ++i)
+                veffo[(size_t(w) * n_pd + j) * own_stride + i] = f.eff[size_t(j) * S + bw.own[w][i]];
     std::vector<double> params = m->params;
     if (params.empty()) params.push_back(0.0);
     // B fragments of eps^T for the MFMA third-body variant
@@ -639,6 +648,7 @@ int load_mechanism(const char* path, pyro_mech** out) {
         {eps_frag.data(), eps_frag.size() * sizeof(double), 0},
         {f.eff.data(), f.eff.size() * sizeof(double), 0},
         {nu_frag.data(), nu_frag.size() * sizeof(double), 0},
+        {veffo.data(), veffo.size() * sizeof(double), 0},
     };
     size_t total = 0;
     for (auto& p : parts) {
@@ -709,6 +719,7 @@ int load_mechanism(const char* path, pyro_mech** out) {
     d.eps_frag = reinterpret_cast<const double*>(base + parts[23].off);
     v.eff = reinterpret_cast<const double*>(base + parts[24].off);
     d.nu_frag = reinterpret_cast<const double*>(base + parts[25].off);
+    v.effo = reinterpret_cast<const double*>(base + parts[26].off);
     // the reverse sweep keeps the efficiencies in LDS when they fit beside its
     // tile (PYRO_VJP_SCALAR_EFFICIENCIES=1 keeps them in the scalar tables)
     const char* scalar_eff = std::getenv("PYRO_VJP_SCALAR_EFFICIENCIES");

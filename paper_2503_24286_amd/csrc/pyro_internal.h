@@ -136,6 +136,7 @@ struct DevSched {
     const uint32_t* gent;
     const int32_t* pd_list;              // [waves][kMaxPd] third-body rows in chunk order
     const double* eff;                   // [n_pd][S] third-body efficiencies
+    const double* effo;                  // [waves][n_pd][MAXOWN] by owned species
 };
 
 struct DevMech {
