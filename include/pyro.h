@@ -178,10 +178,6 @@ PYRO_API int pyro_production_rates(const pyro_mech* mech, int64_t n, int64_t ld,
  * The call allocates a temporary workspace on the stream (stream-ordered).
  * FP64 only.  PYRO_E_UNSUPPORTED for mechanisms whose tables exceed the
  * kernel's LDS tile or with more than 16 species per wavefront.
- * The third-body efficiencies are copied into LDS once per launch when they
- * fit beside the tile; the environment variable
- * PYRO_VJP_SCALAR_EFFICIENCIES=1, read by pyro_mech_load, keeps them in the
- * scalar tables instead (same results up to rounding order; for testing).
  */
 PYRO_API int pyro_production_rates_vjp(const pyro_mech* mech, int64_t n, int64_t ld,
                                        const double* rho, const double* T,

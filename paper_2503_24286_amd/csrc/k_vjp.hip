@@ -254,14 +254,9 @@ __global__ __launch_bounds__(kVjpWaves * 64) void vjp_kernel(
     unsigned char* bufs = lds + size_t(m.S) * kVRow;
     double* mbar = reinterpret_cast<double*>(bufs);                           // after the loop
     double* tb = mbar + size_t(m.n_pd) * kTile;                               // after the loop
-    // the efficiencies [n_pd][S], when staged, stay in LDS for the whole launch
-    double* epsl = reinterpret_cast<double*>(bufs + vjp_region_bytes(m.n_pd));
-    const size_t eps_bytes = sc.eps_lds ? size_t(m.n_pd) * m.S * 8 : 0;
-    double* pacc = reinterpret_cast<double*>(bufs + vjp_region_bytes(m.n_pd) + eps_bytes);
+    double* pacc = reinterpret_cast<double*>(bufs + vjp_region_bytes(m.n_pd)); // [R + n_fo][3]
     const int n_rows = m.R + m.n_fo;
     for (int i = threadIdx.x; i < 3 * n_rows; i += kVjpWaves * 64) pacc[i] = 0.0;
-    if (sc.eps_lds)
-        for (int i = threadIdx.x; i < m.n_pd * m.S; i += kVjpWaves * 64) epsl[i] = cst(sc.eff)[i];
 
     const int nown = cst(sc.n_own)[w];
     const cptr<int32_t> own = cst(sc.own) + w * kMaxOwn;
@@ -302,13 +297,9 @@ __global__ __launch_bounds__(kVjpWaves * 64) void vjp_kernel(
         double Mr[MAXPD];
 #pragma unroll
         for (int i = 0; i < MAXPD; ++i) Mr[i] = 0.0;
-        if (npdw > 0 && sc.eps_lds) {
-            // efficiency rows of this wave's reactions (unused queue slots
-            // repeat the first row; their values are never read)
-            const cptr<int32_t> pl = cst(sc.pd_list) + w * kMaxPd;
-            int roff[MAXPD];
-#pragma unroll
-            for (int i = 0; i < MAXPD; ++i) roff[i] = (i < npdw ? pl[i] : pl[0]) * m.S;
+        if (npdw > 0) {
+            // scalar efficiencies of the wave's queue slots, MAXPD per species
+            const cptr<double> ew = cst(sc.effw) + size_t(w) * m.S * MAXPD;
             int k = 0;
             for (; k + 4 <= m.S; k += 4) {
                 double ck[4];
@@ -319,31 +310,12 @@ __global__ __launch_bounds__(kVjpWaves * 64) void vjp_kernel(
                 for (int u = 0; u < 4; ++u)
 #pragma unroll
                     for (int i = 0; i < MAXPD; ++i)
-                        Mr[i] = fma(epsl[roff[i] + k + u], ck[u], Mr[i]);
+                        Mr[i] = fma(ew[(k + u) * MAXPD + i], ck[u], Mr[i]);
             }
             for (; k < m.S; ++k) {
                 const double ck = reinterpret_cast<const double*>(lds + k * kVRow)[lane];
 #pragma unroll
-                for (int i = 0; i < MAXPD; ++i) Mr[i] = fma(epsl[roff[i] + k], ck, Mr[i]);
-            }
-        } else if (npdw > 0) {
-            const cptr<double> ew = cst(sc.effw) + size_t(w) * m.S * kMaxPd;
-            int k = 0;
-            for (; k + 4 <= m.S; k += 4) {
-                double ck[4];
-#pragma unroll
-                for (int u = 0; u < 4; ++u)
-                    ck[u] = reinterpret_cast<const double*>(lds + (k + u) * kVRow)[lane];
-#pragma unroll
-                for (int u = 0; u < 4; ++u)
-#pragma unroll
-                    for (int i = 0; i < MAXPD; ++i)
-                        Mr[i] = fma(ew[(k + u) * kMaxPd + i], ck[u], Mr[i]);
-            }
-            for (; k < m.S; ++k) {
-                const double ck = reinterpret_cast<const double*>(lds + k * kVRow)[lane];
-#pragma unroll
-                for (int i = 0; i < MAXPD; ++i) Mr[i] = fma(ew[k * kMaxPd + i], ck, Mr[i]);
+                for (int i = 0; i < MAXPD; ++i) Mr[i] = fma(ew[k * MAXPD + i], ck, Mr[i]);
             }
         }
 
@@ -572,13 +544,10 @@ hipError_t set_lds_own(int bytes) {
 
 }  // namespace
 
-size_t vjp_lds_bytes_for(const pyro_mech* m, bool eps_lds) {
-    const size_t n_pd = size_t(m->n_tb + m->n_fo);
-    return size_t(m->S) * kVRow + vjp_region_bytes(int(n_pd)) +
-           (eps_lds ? n_pd * m->S * 8 : 0) + size_t(m->R + m->n_fo) * 3 * 8;
+size_t vjp_lds_bytes(const pyro_mech* m) {
+    return size_t(m->S) * kVRow + vjp_region_bytes(m->n_tb + m->n_fo) +
+           size_t(m->R + m->n_fo) * 3 * 8;
 }
-
-size_t vjp_lds_bytes(const pyro_mech* m) { return vjp_lds_bytes_for(m, m->vjp_eps_lds); }
 
 hipError_t prepare_vjp(const pyro_mech* m) {
     const size_t bytes = vjp_lds_bytes(m);

@@ -19,7 +19,6 @@
 #include <algorithm>
 #include <array>
 #include <cmath>
-#include <cstdlib>
 #include <cstring>
 #include <fstream>
 #include <numeric>
@@ -548,7 +547,7 @@ int load_mechanism(const char* path, pyro_mech** out) {
         fr[i].a2 = -t[3];
     }
     const int s_pad = (S + 7) / 8 * 8;
-    std::vector<double> effw, veffw;
+    std::vector<double> effw, veffw;  // veffw: the reverse sweep reads veffc instead
     std::vector<int32_t> n_pdw, vn_pdw, own_tab, n_own, vown_tab, vn_own;
     wave_tables(fw, f.eff, pd_row, S, effw, n_pdw, own_tab, n_own);
     wave_tables(bw, f.eff, pd_row, S, veffw, vn_pdw, vown_tab, vn_own);
@@ -567,6 +566,17 @@ int load_mechanism(const char* path, pyro_mech** out) {
         for (int j = 0; j < n_pd; ++j)
             for (size_t i = 0; i < bw.own[w].size() && i < size_t(own_stride); ++i)
                 veffo[(size_t(w) * n_pd + j) * own_stride + i] = f.eff[size_t(j) * S + bw.own[w][i]];
+    // the reverse sweep's efficiencies by (wave, species, queue slot): the
+    // MAXPD values of one species are contiguous (MAXPD = the kernel
+    // instance's third-body-slots-per-wave bound)
+    const int pd_stride = bw.max_pdw <= 4 ? 4 : bw.max_pdw <= 8 ? 8 : 16;
+    std::vector<double> veffc(std::max(size_t(1), size_t(kVjpWaves) * S * pd_stride), 0.0);
+    for (int w = 0; w < kVjpWaves; ++w)
+        for (size_t i = 0; i < bw.pd_of_wave[w].size() && i < size_t(pd_stride); ++i) {
+            const int row = pd_row[bw.pd_of_wave[w][i]];
+            for (int k = 0; k < S; ++k)
+                veffc[(size_t(w) * S + k) * pd_stride + i] = f.eff[size_t(row) * S + k];
+        }
     std::vector<double> params = m->params;
     if (params.empty()) params.push_back(0.0);
     // B fragments of eps^T for the MFMA third-body variant
@@ -639,16 +649,15 @@ int load_mechanism(const char* path, pyro_mech** out) {
         {eff_t.data(), eff_t.size() * sizeof(double), 0},
         {bw.recs.data(), bw.recs.size() * sizeof(RxnRec), 0},
         {comp_d.data(), comp_d.size() * sizeof(double), 0},
-        {veffw.data(), veffw.size() * sizeof(double), 0},
+        {veffc.data(), veffc.size() * sizeof(double), 0},
         {vn_pdw.data(), vn_pdw.size() * sizeof(int32_t), 0},
         {vown_tab.data(), vown_tab.size() * sizeof(int32_t), 0},
         {vn_own.data(), vn_own.size() * sizeof(int32_t), 0},
         {vpd_list.data(), vpd_list.size() * sizeof(int32_t), 0},
         {rxn_kc.data(), rxn_kc.size() * sizeof(double), 0},
         {eps_frag.data(), eps_frag.size() * sizeof(double), 0},
-        {f.eff.data(), f.eff.size() * sizeof(double), 0},
-        {nu_frag.data(), nu_frag.size() * sizeof(double), 0},
         {veffo.data(), veffo.size() * sizeof(double), 0},
+        {nu_frag.data(), nu_frag.size() * sizeof(double), 0},
     };
     size_t total = 0;
     for (auto& p : parts) {
@@ -717,15 +726,8 @@ int load_mechanism(const char* path, pyro_mech** out) {
     v.pd_list = reinterpret_cast<const int32_t*>(base + parts[21].off);
     d.rxn_kc = reinterpret_cast<const double*>(base + parts[22].off);
     d.eps_frag = reinterpret_cast<const double*>(base + parts[23].off);
-    v.eff = reinterpret_cast<const double*>(base + parts[24].off);
+    v.effo = reinterpret_cast<const double*>(base + parts[24].off);
     d.nu_frag = reinterpret_cast<const double*>(base + parts[25].off);
-    v.effo = reinterpret_cast<const double*>(base + parts[26].off);
-    // the reverse sweep keeps the efficiencies in LDS when they fit beside its
-    // tile (PYRO_VJP_SCALAR_EFFICIENCIES=1 keeps them in the scalar tables)
-    const char* scalar_eff = std::getenv("PYRO_VJP_SCALAR_EFFICIENCIES");
-    m->vjp_eps_lds = n_pd > 0 && vjp_lds_bytes_for(m, true) <= size_t(160 * 1024) &&
-                     !(scalar_eff && scalar_eff[0] == '1');
-    v.eps_lds = m->vjp_eps_lds ? 1 : 0;
     err = prepare_production_rates(m);
     if (err == hipSuccess) err = prepare_vjp(m);
     if (err != hipSuccess) {

@@ -123,9 +123,9 @@ __device__ inline double from_top16(uint32_t top) {
 // reaction slots, species owned per wave, gathering lists.
 struct DevSched {
     int32_t n_chunks;
-    int32_t eps_lds;                     // reverse sweep: efficiencies staged in LDS
+    int32_t pad;
     const RxnRec* rxn;                   // [n_chunks][waves][rpw]
-    const double* effw;                  // [waves][S][kMaxPd] efficiencies by wave slot
+    const double* effw;                  // [waves][S][MAXPD] efficiencies by queue slot
     const int32_t* n_pdw;                // [waves]
     const int32_t* own;                  // [waves][kMaxOwn]
     const int32_t* n_own;                // [waves]
@@ -135,7 +135,6 @@ struct DevSched {
     // bits of the double x (exact for small integers)
     const uint32_t* gent;
     const int32_t* pd_list;              // [waves][kMaxPd] third-body rows in chunk order
-    const double* eff;                   // [n_pd][S] third-body efficiencies
     const double* effo;                  // [waves][n_pd][MAXOWN] by owned species
 };
 
@@ -188,7 +187,6 @@ struct pyro_mech {
     int vjp_max_own = 0;                 // the same for the reverse-sweep schedule
     int vjp_max_pdw = 0;
     bool kc_ok = false;                  // every reaction's species share one T_mid
-    bool vjp_eps_lds = false;            // the reverse sweep stages the efficiencies in LDS
     int wdot_variant = PYRO_WDOT_SPECIES_EQUILIBRIUM;
     int n_cu = 0;                        // compute units of the device
     std::vector<double> W;               // host copy
@@ -239,7 +237,6 @@ hipError_t launch_production_rates_vjp(const pyro_mech* m, int64_t n, int64_t ld
                                        const double* params, hipStream_t stream);
 size_t vjp_lds_bytes(const pyro_mech* m);
 bool nq_supported(const pyro_mech* m);
-size_t vjp_lds_bytes_for(const pyro_mech* m, bool eps_lds);
 hipError_t prepare_vjp(const pyro_mech* m);
 
 }  // namespace pyro

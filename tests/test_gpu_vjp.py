@@ -92,29 +92,6 @@ def test_vjp_matches_complex_step_oracle(lib_mechs, cfg, n):
     _check_vs_oracle(m, rho, T, Y, wbar, Yb, Tb, pb)
 
 
-def test_vjp_with_efficiencies_in_scalar_tables(lib_mechs, monkeypatch):
-    """The path that reads the third-body efficiencies through scalar loads
-    (taken when they do not fit in LDS beside the tile; forced here at load
-    time) matches the oracle and, summing in the same order, the default
-    LDS path bit for bit."""
-    torch, pyro, gms = lib_mechs
-    m = mechs.load_config(1)
-    n = 150
-    T, p, Y, rho = states(1, n, m.S, first=23)
-    wbar = draw_cotangent(2, n, m.S)
-    monkeypatch.setenv("PYRO_VJP_SCALAR_EFFICIENCIES", "1")
-    gm = pyro.Mechanism(mechs.config_path(1))
-    monkeypatch.delenv("PYRO_VJP_SCALAR_EFFICIENCIES")
-    try:
-        announce(f"vjp cfg1 scalar efficiencies n={n}")
-        Yb, Tb, pb = _gpu_vjp(torch, pyro, gm, rho, T, Y, wbar)
-    finally:
-        gm.close()
-    _check_vs_oracle(m, rho, T, Y, wbar, Yb, Tb, pb)
-    Yd, Td, pd = _gpu_vjp(torch, pyro, gms[1], rho, T, Y, wbar)
-    assert np.array_equal(Yb, Yd) and np.array_equal(Tb, Td) and np.array_equal(pb, pd)
-
-
 def test_vjp_degenerate_states(lib_mechs):
     torch, pyro, gms = lib_mechs
     m = mechs.load_config(1)
