@@ -19,7 +19,7 @@
 // A workgroup of 16 wavefronts works on one 64-cell tile at a time (one
 // reaction per wavefront per chunk of 16, from a schedule of its own), with
 // double-buffered chunk planes and one barrier per chunk.  The sums over the
-// tile's cells of xbar (1, ln T, -1/(R T)) are wavefront butterflies; the
+// tile's cells of xbar (1, ln T, -1/(R T)) are one four-value lane sum; the
 // owning wavefront adds them to the workgroup's accumulator in LDS, and a
 // second kernel adds the per-workgroup accumulators in a fixed order, so the
 // results are bitwise reproducible.
@@ -214,20 +214,42 @@ __device__ inline double dpp(double v) {
     return __builtin_bit_cast(double, r);
 }
 
-// Sum over the 64 lanes with DPP row operations (no LDS traffic), in a fixed
-// order; the total lands in lane 63 (other lanes end with partial or
-// unspecified values).  Quads, half rows and rows are summed with quad
-// permutations and mirrors, after which every lane holds its row's sum; row
-// 2's sum is added into row 3 (and row 0's into row 1) by the broadcast of
-// lane 15 of the row below, then lane 31's value (rows 0 + 1) into row 3.
-__device__ inline double wave_sum(double v) {
-    v += dpp<0xb1, 0xf>(v);    // quad_perm [1, 0, 3, 2]
-    v += dpp<0x4e, 0xf>(v);    // quad_perm [2, 3, 0, 1]
-    v += dpp<0x141, 0xf>(v);   // row_half_mirror
-    v += dpp<0x140, 0xf>(v);   // row_mirror
-    v += dpp<0x142, 0xa>(v);   // row_bcast:15 into rows 1 and 3
-    v += dpp<0x143, 0xc>(v);   // row_bcast:31 into rows 2 and 3
-    return v;
+// v[l] + v[l ^ 16] and v[l] + v[l ^ 32]: the row and half-wave swaps of
+// gfx950 (v_permlane16_swap, v_permlane32_swap) applied to both halves of a
+// double; with both operands equal to v, the two results are v and its
+// partner in either order, so their sum is the pair sum in every lane
+__device__ inline double add_xor16(double v) {
+    const int2 h = __builtin_bit_cast(int2, v);
+    const auto lo = __builtin_amdgcn_permlane16_swap(h.x, h.x, false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap(h.y, h.y, false, false);
+    return __builtin_bit_cast(double, int2{int(lo[0]), int(hi[0])}) +
+           __builtin_bit_cast(double, int2{int(lo[1]), int(hi[1])});
+}
+
+__device__ inline double add_xor32(double v) {
+    const int2 h = __builtin_bit_cast(int2, v);
+    const auto lo = __builtin_amdgcn_permlane32_swap(h.x, h.x, false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap(h.y, h.y, false, false);
+    return __builtin_bit_cast(double, int2{int(lo[0]), int(hi[0])}) +
+           __builtin_bit_cast(double, int2{int(lo[1]), int(hi[1])});
+}
+
+// Sums over the 64 lanes of four values at once, in a fixed order and without
+// LDS traffic: afterwards every lane l holds the total of value l & 3.  Two
+// reduce-scatter exchanges inside each quad (each lane keeps one value of a
+// pair and adds its partner's copy of it), then rotations by 4 and 8 within
+// each row and the row and half-wave swaps, all of which keep a lane's
+// position in its quad.  33 VALU instructions against 54 for three separate
+// butterflies.
+__device__ inline double wave_sum4(double a, double b, double c, double d, int lane) {
+    const bool o1 = lane & 1, o2 = lane & 2;
+    const double u = (o1 ? b : a) + dpp<0xb1, 0xf>(o1 ? a : b);   // quad_perm [1, 0, 3, 2]
+    const double v = (o1 ? d : c) + dpp<0xb1, 0xf>(o1 ? c : d);
+    double z = (o2 ? v : u) + dpp<0x4e, 0xf>(o2 ? u : v);          // quad_perm [2, 3, 0, 1]
+    z += dpp<0x124, 0xf>(z);   // row_ror:4
+    z += dpp<0x128, 0xf>(z);   // row_ror:8
+    z = add_xor16(z);
+    return add_xor32(z);
 }
 
 // LDS of the reverse sweep: species rows, then a region holding the two
@@ -339,27 +361,15 @@ __global__ __launch_bounds__(kVjpWaves * 64) void vjp_kernel(
                 // the loop the queue's tail holds them in chunk order
                 if (r.cls >= kThirdBody) Mr[MAXPD - 1] = o.Mbar;
                 tbar += o.Tbar;
-                // cell sums of xbar (1, ln T, -1/(R T)) into this reaction's rows
-                const double s0 = wave_sum(o.xbar);
-                const double s1 = wave_sum(o.xbar * cs.lnT);
-                const double s2 = wave_sum(-o.xbar * cs.invRT());
-                double t0 = 0.0, t1 = 0.0, t2 = 0.0;
-                if (r.cls >= kLindemann) {
-                    t0 = wave_sum(o.xbar0);
-                    t1 = wave_sum(o.xbar0 * cs.lnT);
-                    t2 = wave_sum(-o.xbar0 * cs.invRT());
-                }
-                if (lane == 63) {
-                    double* pa = pacc + 3 * r.prow;
-                    pa[0] += s0;
-                    pa[1] += s1;
-                    pa[2] += s2;
-                    if (r.cls >= kLindemann) {
-                        double* pl = pacc + 3 * (m.R + r.fo);
-                        pl[0] += t0;
-                        pl[1] += t1;
-                        pl[2] += t2;
-                    }
+                // cell sums of xbar (1, ln T, -1/(R T)) into this reaction's
+                // rows: lanes 0, 1, 2 hold the three totals
+                const double sx = wave_sum4(o.xbar, o.xbar * cs.lnT, -o.xbar * cs.invRT(), 0.0, lane);
+                double sf = 0.0;
+                if (r.cls >= kLindemann)
+                    sf = wave_sum4(o.xbar0, o.xbar0 * cs.lnT, -o.xbar0 * cs.invRT(), 0.0, lane);
+                if (lane < 3) {
+                    pacc[3 * r.prow + lane] += sx;
+                    if (r.cls >= kLindemann) pacc[3 * (m.R + r.fo) + lane] += sf;
                 }
             }
             __syncthreads();
