@@ -216,8 +216,8 @@ def surrogate_leg(args, log):
     """Config-4 surrogate: train an ensemble on exact-kernel labels of
     ``--train-states`` seeded states with the library's own BF16 kernels,
     calibrate the fallback thresholds on 2^20 held-out states for each
-    target error, then evaluate on ``--cells`` fresh states with the exact
-    kernel as the judge of the error."""
+    target error, then evaluate on ``--cells`` fresh states, errors measured
+    against the exact kernel."""
     import numpy as np
     import torch
 
@@ -256,7 +256,7 @@ def surrogate_leg(args, log):
             Y[:, a:a + Tc.shape[0]] = Yc
         return T, p, Y
 
-    # calibration on held-out states, the exact kernel as the judge
+    # calibration on held-out states, errors measured against the exact kernel
     Th, ph, Yh = draw(1 << 20, SEEDS["surrogate_heldout"])
     Td, pd, Yd = (torch.from_numpy(x).cuda() for x in (Th, ph, Yh))
     rho, w_ex = sur.label(gm, Td, pd, Yd)
@@ -347,7 +347,7 @@ def main():
     if args.gpus != 1 or world != 1:
         print("bench.py runs on exactly one GPU: the cells are independent, so more GPUs "
               "would each run this same per-GPU workload on their own share; "
-              "multi-GPU runs are not part of this build.", file=sys.stderr)
+              "this benchmark runs one GPU only.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
