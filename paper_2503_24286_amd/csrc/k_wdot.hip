@@ -47,7 +47,6 @@ namespace {
 
 constexpr int kRow = kTile * 16;          // bytes per species row: C[64] then G[64]
 constexpr int kRowC = kTile * 8;          // RKC variant: C[64]
-constexpr int kQBuf = kChunk * kTile * 8; // bytes per chunk buffer
 
 struct CG {
     double c, g;
@@ -191,8 +190,8 @@ __device__ inline double rate_of_progress(const DevMech& m, const RxnRec& r,
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-template <int MAXOWN, int MAXPD, bool RKC, bool MM, bool NQ>
-__global__ __launch_bounds__(kWaves * 64) void wdot_f64_kernel(
+template <int WAVES, int MAXOWN, int MAXPD, bool RKC, bool MM, bool NQ>
+__global__ __launch_bounds__(WAVES * 64) void wdot_f64_kernel(
     DevMech m, int64_t n, int64_t ld, const double* __restrict__ rho,
     const double* __restrict__ T, const double* __restrict__ Y,
     double* __restrict__ wdot, const double* __restrict__ params,
@@ -249,12 +248,14 @@ __global__ __launch_bounds__(kWaves * 64) void wdot_f64_kernel(
 
     constexpr int rowb = RKC ? kRowC : kRow;
     unsigned char* qbase = lds + size_t(m.S) * rowb;
-    double* Ml = reinterpret_cast<double*>(qbase + 2 * kQBuf);  // MM: [n_pd16][64]
+    constexpr int qbuf = WAVES * kRxnPerWave * kTile * 8;     // bytes per chunk buffer
+    static_assert(!NQ || WAVES == kWaves, "the MFMA net rates assume kWaves wavefronts");
+    double* Ml = reinterpret_cast<double*>(qbase + 2 * qbuf);  // MM: [n_pd16][64]
     if constexpr (MM) {
         // ---- the tile's third-body concentrations on the matrix cores: wave w
         // takes the 16-cell x 16-reaction output blocks w, w + 8, ...
         const int n_pb = (m.n_pd + 15) / 16, n_ks = (m.S + 3) / 4;
-        for (int t = w; t < 4 * n_pb; t += kWaves) {
+        for (int t = w; t < 4 * n_pb; t += WAVES) {
             const int cb = t & 3, pb = t >> 2;
             const double* eb = m.eps_frag + size_t(pb) * n_ks * 64 + lane;
             d4 acc = {0.0, 0.0, 0.0, 0.0};
@@ -297,7 +298,7 @@ __global__ __launch_bounds__(kWaves * 64) void wdot_f64_kernel(
     d4 wacc[2] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
     static_assert(kRxnPerWave == 2, "the reaction phase handles reactions in pairs");
     for (int ch = 0; ch < m.n_chunks; ++ch) {
-        unsigned char* qb = qbase + (ch & 1) * kQBuf;
+        unsigned char* qb = qbase + (ch & 1) * qbuf;
         // NQ: this chunk's B fragments of nu, loaded before the rates are evaluated
         double nub[2][4];
         if constexpr (NQ) {
@@ -307,7 +308,7 @@ __global__ __launch_bounds__(kWaves * 64) void wdot_f64_kernel(
                 for (int kk = 0; kk < 4; ++kk)
                     nub[b][kk] = m.nu_frag[((size_t(ch) * 4 + nq_sb + 2 * b) * 4 + kk) * 64 + lane];
         }
-        const RxnRec* rb = m.rxn + (size_t(ch) * kWaves + w) * kRxnPerWave;
+        const RxnRec* rb = m.rxn + (size_t(ch) * WAVES + w) * kRxnPerWave;
         const RxnRec r0 = rb[0];
         const RxnRec r1 = rb[1];
         // both Arrhenius exponentials in one block, so they interleave
@@ -322,7 +323,7 @@ __global__ __launch_bounds__(kWaves * 64) void wdot_f64_kernel(
             M0 = r0.cls >= kThirdBody ? pop_front(Mr) : 1.0;
             M1 = r1.cls >= kThirdBody ? pop_front(Mr) : 1.0;
         }
-        const cptr<double> kc = cst(m.rxn_kc) + (size_t(ch) * kWaves + w) * kRxnPerWave * 16;
+        const cptr<double> kc = cst(m.rxn_kc) + (size_t(ch) * WAVES + w) * kRxnPerWave * 16;
         if (r0.cls != kNoReaction)
             *reinterpret_cast<double*>(qb + r0.qoff + lane * 8) = rate_of_progress<RKC>(
                 m, r0, params, lds, lane, kf0, M0, Tc, lnT, invT, invRT, rtp, irtp, kc);
@@ -348,7 +349,7 @@ __global__ __launch_bounds__(kWaves * 64) void wdot_f64_kernel(
         }
         // gather: the boundaries of all owned species in one scalar load,
         // then each species' entries in pairs
-        const int32_t* gp = m.gptr + (size_t(ch) * kWaves + w) * (kMaxOwn + 1);
+        const int32_t* gp = m.gptr + (size_t(ch) * WAVES + w) * (kMaxOwn + 1);
         int32_t bound[MAXOWN + 1];
 #pragma unroll
         for (int i = 0; i <= MAXOWN; ++i) bound[i] = gp[i];
@@ -395,23 +396,25 @@ __global__ __launch_bounds__(kWaves * 64) void wdot_f64_kernel(
     }
 }
 
-template <int MAXOWN, int MAXPD, bool RKC, bool MM, bool NQ>
+template <int WAVES, int MAXOWN, int MAXPD, bool RKC, bool MM, bool NQ>
 hipError_t launch_f64(const pyro_mech* m, int64_t n, int64_t ld, const double* rho,
                       const double* T, const double* Y, double* wdot,
                       const double* params, hipStream_t stream, const int64_t* n_dev) {
     const size_t lds = production_rates_lds_bytes(m, RKC, MM);
     const int64_t blocks = (n + kTile - 1) / kTile;
-    hipLaunchKernelGGL((wdot_f64_kernel<MAXOWN, MAXPD, RKC, MM, NQ>), dim3(unsigned(blocks)),
-                       dim3(kWaves * 64), lds, stream, m->dev, n, ld, rho, T, Y, wdot,
+    hipLaunchKernelGGL((wdot_f64_kernel<WAVES, MAXOWN, MAXPD, RKC, MM, NQ>), dim3(unsigned(blocks)),
+                       dim3(WAVES * 64), lds, stream, m->dev, n, ld, rho, T, Y, wdot,
                        params ? params : m->dev.params, n_dev);
     return hipGetLastError();
 }
 
-// Kernel instances: (species owned per wave, [M] slots per wave, variant).
-template <int MAXOWN, int MAXPD, bool RKC, bool MM, bool NQ>
+// Kernel instances: (wavefronts, species owned per wave, [M] slots per wave,
+// variant).  With 2 kWaves wavefronts (large mechanisms, reaction variant
+// only) a wave owns at most 16 species.
+template <int WAVES, int MAXOWN, int MAXPD, bool RKC, bool MM, bool NQ>
 hipError_t set_lds(int bytes) {
     return hipFuncSetAttribute(
-        reinterpret_cast<const void*>(&wdot_f64_kernel<MAXOWN, MAXPD, RKC, MM, NQ>),
+        reinterpret_cast<const void*>(&wdot_f64_kernel<WAVES, MAXOWN, MAXPD, RKC, MM, NQ>),
         hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
@@ -420,25 +423,44 @@ template <int MAXPD, bool RKC, bool MM, bool NQ>
 hipError_t dispatch_own(const pyro_mech* m, int64_t n, int64_t ld, const double* r,
                         const double* t, const double* y, double* o, const double* params,
                         hipStream_t stream, const int64_t* nd) {
-    if (m->max_own <= 8) return launch_f64<8, MAXPD, RKC, MM, NQ>(m, n, ld, r, t, y, o, params, stream, nd);
+    if constexpr (RKC && !NQ) {
+        if (m->fw_waves != kWaves) {
+            if (m->max_own <= 8)
+                return launch_f64<2 * kWaves, 8, MAXPD, RKC, MM, false>(m, n, ld, r, t, y, o, params, stream, nd);
+            return launch_f64<2 * kWaves, 16, MAXPD, RKC, MM, false>(m, n, ld, r, t, y, o, params, stream, nd);
+        }
+    }
+    if (m->max_own <= 8) return launch_f64<kWaves, 8, MAXPD, RKC, MM, NQ>(m, n, ld, r, t, y, o, params, stream, nd);
     if (NQ || m->max_own <= 16)
-        return launch_f64<16, MAXPD, RKC, MM, NQ>(m, n, ld, r, t, y, o, params, stream, nd);
-    if (m->max_own <= 32) return launch_f64<32, MAXPD, RKC, MM, false>(m, n, ld, r, t, y, o, params, stream, nd);
-    return launch_f64<64, MAXPD, RKC, MM, false>(m, n, ld, r, t, y, o, params, stream, nd);
+        return launch_f64<kWaves, 16, MAXPD, RKC, MM, NQ>(m, n, ld, r, t, y, o, params, stream, nd);
+    if (m->max_own <= 32) return launch_f64<kWaves, 32, MAXPD, RKC, MM, false>(m, n, ld, r, t, y, o, params, stream, nd);
+    return launch_f64<kWaves, 64, MAXPD, RKC, MM, false>(m, n, ld, r, t, y, o, params, stream, nd);
 }
 
 template <bool RKC, bool MM, bool NQ>
-hipError_t set_lds_variant(int bytes) {
+hipError_t set_lds_variant(const pyro_mech* m, int bytes) {
     hipError_t e = hipSuccess;
+    if constexpr (RKC && !NQ) {
+        if (m->fw_waves != kWaves) {
+            const hipError_t big[] = {
+                set_lds<2 * kWaves, 8, 8, RKC, MM, false>(bytes),
+                set_lds<2 * kWaves, 16, 8, RKC, MM, false>(bytes),
+                MM ? hipSuccess : set_lds<2 * kWaves, 8, 16, RKC, MM, false>(bytes),
+                MM ? hipSuccess : set_lds<2 * kWaves, 16, 16, RKC, MM, false>(bytes)};
+            for (hipError_t x : big)
+                if (x != hipSuccess) e = x;
+            return e;
+        }
+    }
     // the MFMA third-body variant holds no per-wave [M] slots: one MAXPD instance
     const hipError_t all[] = {
-        set_lds<8, 8, RKC, MM, NQ>(bytes),  set_lds<16, 8, RKC, MM, NQ>(bytes),
-        NQ ? hipSuccess : set_lds<32, 8, RKC, MM, false>(bytes),
-        NQ ? hipSuccess : set_lds<64, 8, RKC, MM, false>(bytes),
-        MM ? hipSuccess : set_lds<8, 16, RKC, MM, NQ>(bytes),
-        MM ? hipSuccess : set_lds<16, 16, RKC, MM, NQ>(bytes),
-        MM || NQ ? hipSuccess : set_lds<32, 16, RKC, MM, false>(bytes),
-        MM || NQ ? hipSuccess : set_lds<64, 16, RKC, MM, false>(bytes)};
+        set_lds<kWaves, 8, 8, RKC, MM, NQ>(bytes),  set_lds<kWaves, 16, 8, RKC, MM, NQ>(bytes),
+        NQ ? hipSuccess : set_lds<kWaves, 32, 8, RKC, MM, false>(bytes),
+        NQ ? hipSuccess : set_lds<kWaves, 64, 8, RKC, MM, false>(bytes),
+        MM ? hipSuccess : set_lds<kWaves, 8, 16, RKC, MM, NQ>(bytes),
+        MM ? hipSuccess : set_lds<kWaves, 16, 16, RKC, MM, NQ>(bytes),
+        MM || NQ ? hipSuccess : set_lds<kWaves, 32, 16, RKC, MM, false>(bytes),
+        MM || NQ ? hipSuccess : set_lds<kWaves, 64, 16, RKC, MM, false>(bytes)};
     for (hipError_t x : all)
         if (x != hipSuccess) e = x;
     return e;
@@ -456,7 +478,8 @@ hipError_t dispatch_variant(const pyro_mech* m, int64_t n, int64_t ld, const dou
 
 size_t production_rates_lds_bytes(const pyro_mech* m, bool reaction_equilibrium,
                                   bool mfma_third_body) {
-    return size_t(m->S) * (reaction_equilibrium ? kRowC : kRow) + 2 * size_t(kQBuf) +
+    return size_t(m->S) * (reaction_equilibrium ? kRowC : kRow) +
+           2 * size_t(m->fw_waves) * kRxnPerWave * kTile * 8 +
            (mfma_third_body ? size_t((m->n_tb + m->n_fo + 15) / 16 * 16) * kTile * 8 : 0);
 }
 
@@ -468,21 +491,23 @@ hipError_t prepare_production_rates(const pyro_mech* m) {
         if (bytes > 160 * 1024 || (rkc && !m->kc_ok) || (nq && !nq_supported(m))) continue;
         hipError_t x;
         switch (v) {
-            case 0: x = set_lds_variant<false, false, false>(int(bytes)); break;
-            case 1: x = set_lds_variant<true, false, false>(int(bytes)); break;
-            case 2: x = set_lds_variant<false, true, false>(int(bytes)); break;
-            case 3: x = set_lds_variant<true, true, false>(int(bytes)); break;
-            case 4: x = set_lds_variant<false, false, true>(int(bytes)); break;
-            case 5: x = set_lds_variant<true, false, true>(int(bytes)); break;
-            case 6: x = set_lds_variant<false, true, true>(int(bytes)); break;
-            default: x = set_lds_variant<true, true, true>(int(bytes));
+            case 0: x = set_lds_variant<false, false, false>(m, int(bytes)); break;
+            case 1: x = set_lds_variant<true, false, false>(m, int(bytes)); break;
+            case 2: x = set_lds_variant<false, true, false>(m, int(bytes)); break;
+            case 3: x = set_lds_variant<true, true, false>(m, int(bytes)); break;
+            case 4: x = set_lds_variant<false, false, true>(m, int(bytes)); break;
+            case 5: x = set_lds_variant<true, false, true>(m, int(bytes)); break;
+            case 6: x = set_lds_variant<false, true, true>(m, int(bytes)); break;
+            default: x = set_lds_variant<true, true, true>(m, int(bytes));
         }
         if (x != hipSuccess) e = x;
     }
     return e;
 }
 
-bool nq_supported(const pyro_mech* m) { return m->S <= 64 && m->max_own <= 16; }
+bool nq_supported(const pyro_mech* m) {
+    return m->S <= 64 && m->max_own <= 16 && m->fw_waves == kWaves;
+}
 
 hipError_t launch_production_rates(const pyro_mech* m, int64_t n, int64_t ld, int dtype,
                                    const void* rho, const void* T, const void* Y,

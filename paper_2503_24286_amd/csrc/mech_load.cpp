@@ -427,6 +427,9 @@ int load_mechanism(const char* path, pyro_mech** out) {
         for (int k : prod[j]) m->kc_ok = m->kc_ok && f.trange[3 * k + 1] == tm;
     }
     const bool fits_species = production_rates_lds_bytes(m, false) <= 160 * 1024;
+    // when the species rows exclude a second workgroup per CU, one workgroup
+    // of twice the wavefronts keeps four of them per SIMD
+    if (!fits_species) m->fw_waves = 2 * kWaves;
     const bool fits_reaction = m->kc_ok && production_rates_lds_bytes(m, true) <= 160 * 1024;
     if (!fits_species && !fits_reaction) {
         delete m;
@@ -453,7 +456,8 @@ int load_mechanism(const char* path, pyro_mech** out) {
         for (auto& e : part[k]) g_part[e[0]].push_back(k);
     }
     HostSched fw, bw;
-    if (int rc = build_schedule(sin, kWaves, kRxnPerWave, kMaxOwn, kTile * 16, g_net, fw)) {
+    if (int rc = build_schedule(sin, m->fw_waves, kRxnPerWave, m->fw_waves == kWaves ? kMaxOwn : 16,
+                                kTile * 16, g_net, fw)) {
         delete m;
         return rc;
     }
@@ -611,10 +615,11 @@ int load_mechanism(const char* path, pyro_mech** out) {
     }
 
     // B fragments of the net coefficients per forward chunk (S <= 64)
-    std::vector<double> nu_frag(S <= 64 ? size_t(std::max(n_chunks, 1)) * 4 * 4 * 64 : 1, 0.0);
-    if (S <= 64)
+    const bool nq_table = S <= 64 && m->fw_waves == kWaves;
+    std::vector<double> nu_frag(nq_table ? size_t(std::max(n_chunks, 1)) * 4 * 4 * 64 : 1, 0.0);
+    if (nq_table)
         for (int c = 0; c < n_chunks; ++c)
-            for (int slot = 0; slot < kChunk; ++slot) {
+            for (int slot = 0; slot < kChunk; ++slot) {   // (only with kWaves waves)
                 const RxnRec& r = recs[size_t(c) * kChunk + slot];
                 if (r.cls == kNoReaction) continue;
                 const int j = r.prow;

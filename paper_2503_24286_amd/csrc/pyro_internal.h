@@ -146,14 +146,14 @@ struct DevMech {
     int32_t pad;
     double t_mid_group[kMaxTmidGroups];
     const SpeciesRec* species;           // [S]
-    const RxnRec* rxn;                   // [n_chunks][kWaves][kRxnPerWave]
+    const RxnRec* rxn;                   // [n_chunks][waves][kRxnPerWave]
     const FalloffRec* falloff;           // [n_fo]
-    const double* effw;                  // [kWaves][S][kMaxPd] efficiencies by wave slot
-    const int32_t* n_pdw;                // [kWaves] third-body/falloff reactions per wave
+    const double* effw;                  // [waves][S][kMaxPd] efficiencies by wave slot
+    const int32_t* n_pdw;                // [waves] third-body/falloff reactions per wave
     const double* params;                // [R + n_fo][3] default triples
-    const int32_t* own;                  // [kWaves][kMaxOwn] species owned
-    const int32_t* n_own;                // [kWaves]
-    const int32_t* gptr;                 // [n_chunks][kWaves][kMaxOwn + 1]
+    const int32_t* own;                  // [waves][kMaxOwn] species owned
+    const int32_t* n_own;                // [waves]
+    const int32_t* gptr;                 // [n_chunks][waves][kMaxOwn + 1]
     const GatherEntry* gent;             // gathering entries
     const NewtonSpecies* newton;         // [S]
     const double* w;                     // [S] molar masses
@@ -162,7 +162,7 @@ struct DevMech {
     const double* eff_t;                 // [S][n_pd] efficiencies by species
     // reaction-equilibrium variant: per forward slot, the combined Gibbs
     // coefficients sum_k nu_kj c_k (low range [7], high range [7], T_mid, 0)
-    const double* rxn_kc;                // [n_chunks][kWaves][kRxnPerWave][16]
+    const double* rxn_kc;                // [n_chunks][waves][kRxnPerWave][16]
     // MFMA third-body variant: B fragments of eps^T, [pd block][K-step][lane]
     // = eps[16 pb + l%16][4 kk + l/16] (zero outside n_pd x S)
     const double* eps_frag;
@@ -188,6 +188,9 @@ struct pyro_mech {
     int vjp_max_pdw = 0;
     bool kc_ok = false;                  // every reaction's species share one T_mid
     int wdot_variant = PYRO_WDOT_SPECIES_EQUILIBRIUM;
+    // wavefronts of the production-rate workgroup: kWaves, or 2 kWaves for
+    // mechanisms whose species rows leave room for only one workgroup per CU
+    int fw_waves = pyro::kWaves;
     int n_cu = 0;                        // compute units of the device
     std::vector<double> W;               // host copy
     std::vector<double> params;          // host copy of the default triples
