@@ -317,7 +317,9 @@ PYRO_API int pyro_surrogate_outputs(const pyro_mech* mech, const pyro_surrogate*
  * ||A omega|| / || |A| |omega| || is below thr_resid (both strictly).  fell_back[n] (device u8) marks those
  * cells, *n_fallback (device int64) counts them; indicators, if not NULL,
  * receives the spread [n] then the residual [n].  thr = 0 sends every cell
- * to the exact kernel, +inf none.
+ * to the exact kernel, +inf none; when a threshold admits no cell (<= 0 or
+ * NaN) and indicators is NULL, the network is not run and the call is the
+ * exact kernel on every cell (same wdot, flags and count).
  */
 PYRO_API int pyro_surrogate_eval(const pyro_mech* mech, const pyro_surrogate* sur,
                                  int64_t n, int64_t ld, const double* rho, const double* T,

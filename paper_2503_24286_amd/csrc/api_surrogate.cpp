@@ -339,6 +339,14 @@ int pyro_surrogate_eval(const pyro_mech* m, const pyro_surrogate* sur, int64_t n
         return fail(PYRO_E_ARG, "workspace too small: need " + std::to_string(need) + " bytes");
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipError_t e;
+    if (!indicators && !(thr_spread > 0.0 && thr_resid > 0.0)) {
+        // no cell can be kept (spread and residual are never negative): the
+        // call is the exact kernel on every cell, the network is not run
+        e = launch_fallback_all(n, fell_back, n_fallback, s);
+        if (e == hipSuccess)
+            e = launch_production_rates(m, n, ld, PYRO_F64, rho, T, Y, wdot, nullptr, s, nullptr);
+        return e == hipSuccess ? PYRO_OK : hip_fail(e, "surrogate launch");
+    }
     const Packed p = pack(sur, workspace, s, &e);
     const int64_t nb = compaction_blocks(n);
     unsigned char* q = p.rest;

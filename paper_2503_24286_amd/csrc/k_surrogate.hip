@@ -154,6 +154,14 @@ __global__ __launch_bounds__(kBlock) void scatter_kernel(int S, int64_t n, int64
     for (int k = 0; k < S; ++k) wdot[size_t(k) * ld + c] = wc[size_t(k) * n + i];
 }
 
+// every cell sent to the exact kernel: flags set, the count is n
+__global__ __launch_bounds__(kBlock) void fallback_all_kernel(int64_t n, uint8_t* __restrict__ flag,
+                                                              int64_t* __restrict__ total) {
+    const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+    if (i < n) flag[i] = 1;
+    if (i == 0) *total = n;
+}
+
 unsigned grid(int64_t n, int b) { return unsigned((n + b - 1) / b); }
 
 }  // namespace
@@ -184,6 +192,12 @@ hipError_t launch_compaction(int64_t n, const uint8_t* flag, int64_t* counts, in
     hipLaunchKernelGGL(scan_counts_kernel, dim3(1), dim3(kScanBlock), 0, stream, nb, counts, total);
     hipLaunchKernelGGL(compact_kernel, dim3(unsigned(nb)), dim3(kScanBlock), 0, stream, n, flag,
                        counts, idx);
+    return hipGetLastError();
+}
+
+hipError_t launch_fallback_all(int64_t n, uint8_t* flag, int64_t* total, hipStream_t stream) {
+    hipLaunchKernelGGL(fallback_all_kernel, dim3(grid(n, kBlock)), dim3(kBlock), 0, stream, n, flag,
+                       total);
     return hipGetLastError();
 }
 

@@ -38,6 +38,7 @@ hipError_t launch_fused(const pyro_mech* m, int hidden, int members, int64_t n, 
 int64_t compaction_blocks(int64_t n);
 hipError_t launch_compaction(int64_t n, const uint8_t* flag, int64_t* counts, int64_t* total,
                              int64_t* idx, hipStream_t stream);
+hipError_t launch_fallback_all(int64_t n, uint8_t* flag, int64_t* total, hipStream_t stream);
 hipError_t launch_gather(int S, int64_t n, int64_t ld, const int64_t* count, const int64_t* idx,
                          const double* rho, const double* T, const double* Y, double* rc,
                          double* Tc, double* Yc, hipStream_t stream);

@@ -305,11 +305,16 @@ def test_eval_threshold_zero_is_the_exact_kernel_bitwise(env, cfg, n):
     T, p, Y, rho = states(cfg, n, m.S, first=777)
     r, t, y = to_dev(torch, rho, T, Y)
     announce(f"surrogate eval thr=0 cfg{cfg} n={n}")
-    w, flags, count, _ = model.eval(gm, r, t, y, thr_spread=0.0, thr_resid=0.0)
-    exact = pyro.production_rates(gm, r, t, y)
-    torch.cuda.synchronize()
-    assert int(count.item()) == n and bool((flags == 1).all())
-    assert np.array_equal(w.cpu().numpy().view(np.uint64), exact.cpu().numpy().view(np.uint64))
+    exact = pyro.production_rates(gm, r, t, y).cpu().numpy().view(np.uint64)
+    # without indicators the call skips the network; with them it runs the
+    # network and falls back on every cell: both are the exact kernel
+    for want_ind in (False, True):
+        w, flags, count, ind = model.eval(gm, r, t, y, thr_spread=0.0, thr_resid=0.0,
+                                          indicators=want_ind)
+        torch.cuda.synchronize()
+        assert (ind is not None) == want_ind
+        assert int(count.item()) == n and bool((flags == 1).all())
+        assert np.array_equal(w.cpu().numpy().view(np.uint64), exact)
 
 
 def _host_eval(model, m, Zs):
