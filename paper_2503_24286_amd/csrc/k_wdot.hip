@@ -278,11 +278,11 @@ __global__ __launch_bounds__(WAVES * 64) void wdot_f64_kernel(
 #pragma unroll
     for (int i = 0; i < MAXPD; ++i) Mr[i] = 0.0;
     if (!MM && m.n_pdw[w] > 0) {
-        const double* ew = m.effw + size_t(w) * m.S * kMaxPd;
+        const double* ew = m.effw + size_t(w) * m.S * MAXPD;
         for (int k = 0; k < m.S; ++k) {
             const double ck = reinterpret_cast<const double*>(lds + k * rowb)[lane];
 #pragma unroll
-            for (int i = 0; i < MAXPD; ++i) Mr[i] = fma(ew[k * kMaxPd + i], ck, Mr[i]);
+            for (int i = 0; i < MAXPD; ++i) Mr[i] = fma(ew[k * MAXPD + i], ck, Mr[i]);
         }
     }
 

@@ -551,9 +551,19 @@ int load_mechanism(const char* path, pyro_mech** out) {
         fr[i].a2 = -t[3];
     }
     const int s_pad = (S + 7) / 8 * 8;
-    std::vector<double> effw, veffw;  // veffw: the reverse sweep reads veffc instead
+    std::vector<double> effw_wide, veffw;  // the kernels read the compact tables below
     std::vector<int32_t> n_pdw, vn_pdw, own_tab, n_own, vown_tab, vn_own;
-    wave_tables(fw, f.eff, pd_row, S, effw, n_pdw, own_tab, n_own);
+    wave_tables(fw, f.eff, pd_row, S, effw_wide, n_pdw, own_tab, n_own);
+    // the forward [M] pass's efficiencies by (wave, species, queue slot), the
+    // MAXPD values of one species contiguous (MAXPD: the kernel instance's bound)
+    const int fpd_stride = fw.max_pdw <= 8 ? 8 : 16;
+    std::vector<double> effw(std::max(size_t(1), size_t(fw.waves) * S * fpd_stride), 0.0);
+    for (int w = 0; w < fw.waves; ++w)
+        for (size_t i = 0; i < fw.pd_of_wave[w].size() && i < size_t(fpd_stride); ++i) {
+            const int row = pd_row[fw.pd_of_wave[w][i]];
+            for (int k = 0; k < S; ++k)
+                effw[(size_t(w) * S + k) * fpd_stride + i] = f.eff[size_t(row) * S + k];
+        }
     wave_tables(bw, f.eff, pd_row, S, veffw, vn_pdw, vown_tab, vn_own);
     // the reverse sweep's third-body rows per wave, in the order its chunks
     // meet them (one reaction per wave per chunk)

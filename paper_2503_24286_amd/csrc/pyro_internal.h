@@ -148,7 +148,7 @@ struct DevMech {
     const SpeciesRec* species;           // [S]
     const RxnRec* rxn;                   // [n_chunks][waves][kRxnPerWave]
     const FalloffRec* falloff;           // [n_fo]
-    const double* effw;                  // [waves][S][kMaxPd] efficiencies by wave slot
+    const double* effw;                  // [waves][S][MAXPD] efficiencies by wave slot
     const int32_t* n_pdw;                // [waves] third-body/falloff reactions per wave
     const double* params;                // [R + n_fo][3] default triples
     const int32_t* own;                  // [waves][kMaxOwn] species owned
