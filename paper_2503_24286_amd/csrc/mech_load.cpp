@@ -202,8 +202,13 @@ struct HostSched {
 
 // row_bytes: the kernel's LDS bytes per species row; participants' offsets
 // in the reaction records are species * row_bytes
+// rank_bias > 0 skews species ownership toward low wave indices: of the
+// waves sharing a SIMD (w, w + 4, ...), the SIMD's arbiter issues the older
+// ones first, so they reach each chunk barrier early and can take more of the
+// gathering (weight 1 + rank_bias * (w / 4) on a wave's load)
 int build_schedule(const SchedInput& in, int waves, int rpw, int own_cap, int row_bytes,
-                   const std::vector<std::vector<int>>& gathered, HostSched& out) {
+                   double rank_bias, const std::vector<std::vector<int>>& gathered,
+                   HostSched& out) {
     const int S = in.S, R = in.R;
     const auto& rtype = *in.rtype;
     const auto& by_species = *in.by_species;
@@ -220,7 +225,10 @@ int build_schedule(const SchedInput& in, int waves, int rpw, int own_cap, int ro
     for (int k : order) {
         int best = -1;
         for (int w = 0; w < waves; ++w)
-            if (int(out.own[w].size()) < own_cap && (best < 0 || load[w] < load[best])) best = w;
+            if (int(out.own[w].size()) < own_cap &&
+                (best < 0 || load[w] * (1.0 + rank_bias * (w / 4)) <
+                                 load[best] * (1.0 + rank_bias * (best / 4))))
+                best = w;
         if (best < 0) return fail(PYRO_E_UNSUPPORTED, "too many species for one workgroup");
         out.own[best].push_back(k);
         load[best] += 2.0 + double(by_species[k].size());
@@ -457,12 +465,12 @@ int load_mechanism(const char* path, pyro_mech** out) {
     }
     HostSched fw, bw;
     if (int rc = build_schedule(sin, m->fw_waves, kRxnPerWave, m->fw_waves == kWaves ? kMaxOwn : 16,
-                                kTile * 16, g_net, fw)) {
+                                kTile * 16, 0.0, g_net, fw)) {
         delete m;
         return rc;
     }
     if (int rc = build_schedule(sin, kVjpWaves, 1, std::max(4, (S + kVjpWaves - 1) / kVjpWaves),
-                                kVjpRow, g_part, bw)) {
+                                kVjpRow, 1.5, g_part, bw)) {
         delete m;
         return rc;
     }
