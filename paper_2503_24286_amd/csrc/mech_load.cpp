@@ -354,22 +354,23 @@ void gather_lists(const HostSched& sc, F entries, std::vector<int32_t>& ptr,
     ent.resize(ent.size() + 2, 0u);  // slack: pairwise loops may read one past
 }
 
-// Per-wave tables of a schedule: efficiencies by (wave, species, wave slot),
-// so that the [M] pass of a wave reads the kMaxPd values of one species with
-// one scalar load, and the owned species.
+// Per-wave tables of a schedule: efficiencies by (wave, species, queue slot),
+// pd_stride values per species (the kernel instance's bound on a wave's
+// third-body reactions, MAXPD), so that the [M] pass of a wave reads one
+// species' values with one scalar load; and the owned species.
 void wave_tables(const HostSched& sc, const std::vector<double>& eff,
-                 const std::vector<int>& pd_row, int S, std::vector<double>& effw,
+                 const std::vector<int>& pd_row, int S, int pd_stride, std::vector<double>& effw,
                  std::vector<int32_t>& n_pdw, std::vector<int32_t>& own_tab,
                  std::vector<int32_t>& n_own) {
-    effw.assign(size_t(sc.waves) * S * kMaxPd, 0.0);
+    effw.assign(std::max(size_t(1), size_t(sc.waves) * S * pd_stride), 0.0);
     n_pdw.assign(sc.waves, 0);
     own_tab.assign(size_t(sc.waves) * kMaxOwn, -1);
     n_own.assign(sc.waves, 0);
     for (int w = 0; w < sc.waves; ++w) {
         n_pdw[w] = int(sc.pd_of_wave[w].size());
-        for (int i = 0; i < n_pdw[w]; ++i) {
+        for (int i = 0; i < n_pdw[w] && i < pd_stride; ++i) {
             const int row = pd_row[sc.pd_of_wave[w][i]];
-            for (int k = 0; k < S; ++k) effw[(size_t(w) * S + k) * kMaxPd + i] = eff[size_t(row) * S + k];
+            for (int k = 0; k < S; ++k) effw[(size_t(w) * S + k) * pd_stride + i] = eff[size_t(row) * S + k];
         }
         n_own[w] = int(sc.own[w].size());
         for (size_t i = 0; i < sc.own[w].size(); ++i) own_tab[w * kMaxOwn + i] = sc.own[w][i];
@@ -559,20 +560,13 @@ int load_mechanism(const char* path, pyro_mech** out) {
         fr[i].a2 = -t[3];
     }
     const int s_pad = (S + 7) / 8 * 8;
-    std::vector<double> effw_wide, veffw;  // the kernels read the compact tables below
+    std::vector<double> effw, veffw;
     std::vector<int32_t> n_pdw, vn_pdw, own_tab, n_own, vown_tab, vn_own;
-    wave_tables(fw, f.eff, pd_row, S, effw_wide, n_pdw, own_tab, n_own);
-    // the forward [M] pass's efficiencies by (wave, species, queue slot), the
-    // MAXPD values of one species contiguous (MAXPD: the kernel instance's bound)
+    // MAXPD of the kernel instances each schedule runs with
     const int fpd_stride = fw.max_pdw <= 8 ? 8 : 16;
-    std::vector<double> effw(std::max(size_t(1), size_t(fw.waves) * S * fpd_stride), 0.0);
-    for (int w = 0; w < fw.waves; ++w)
-        for (size_t i = 0; i < fw.pd_of_wave[w].size() && i < size_t(fpd_stride); ++i) {
-            const int row = pd_row[fw.pd_of_wave[w][i]];
-            for (int k = 0; k < S; ++k)
-                effw[(size_t(w) * S + k) * fpd_stride + i] = f.eff[size_t(row) * S + k];
-        }
-    wave_tables(bw, f.eff, pd_row, S, veffw, vn_pdw, vown_tab, vn_own);
+    const int vpd_stride = bw.max_pdw <= 4 ? 4 : bw.max_pdw <= 8 ? 8 : 16;
+    wave_tables(fw, f.eff, pd_row, S, fpd_stride, effw, n_pdw, own_tab, n_own);
+    wave_tables(bw, f.eff, pd_row, S, vpd_stride, veffw, vn_pdw, vown_tab, vn_own);
     // the reverse sweep's third-body rows per wave, in the order its chunks
     // meet them (one reaction per wave per chunk)
     std::vector<int32_t> vpd_list(size_t(kVjpWaves) * kMaxPd, -1);
@@ -588,17 +582,6 @@ int load_mechanism(const char* path, pyro_mech** out) {
         for (int j = 0; j < n_pd; ++j)
             for (size_t i = 0; i < bw.own[w].size() && i < size_t(own_stride); ++i)
                 veffo[(size_t(w) * n_pd + j) * own_stride + i] = f.eff[size_t(j) * S + bw.own[w][i]];
-    // the reverse sweep's efficiencies by (wave, species, queue slot): the
-    // MAXPD values of one species are contiguous (MAXPD = the kernel
-    // instance's third-body-slots-per-wave bound)
-    const int pd_stride = bw.max_pdw <= 4 ? 4 : bw.max_pdw <= 8 ? 8 : 16;
-    std::vector<double> veffc(std::max(size_t(1), size_t(kVjpWaves) * S * pd_stride), 0.0);
-    for (int w = 0; w < kVjpWaves; ++w)
-        for (size_t i = 0; i < bw.pd_of_wave[w].size() && i < size_t(pd_stride); ++i) {
-            const int row = pd_row[bw.pd_of_wave[w][i]];
-            for (int k = 0; k < S; ++k)
-                veffc[(size_t(w) * S + k) * pd_stride + i] = f.eff[size_t(row) * S + k];
-        }
     std::vector<double> params = m->params;
     if (params.empty()) params.push_back(0.0);
     // B fragments of eps^T for the MFMA third-body variant
@@ -672,7 +655,7 @@ int load_mechanism(const char* path, pyro_mech** out) {
         {eff_t.data(), eff_t.size() * sizeof(double), 0},
         {bw.recs.data(), bw.recs.size() * sizeof(RxnRec), 0},
         {comp_d.data(), comp_d.size() * sizeof(double), 0},
-        {veffc.data(), veffc.size() * sizeof(double), 0},
+        {veffw.data(), veffw.size() * sizeof(double), 0},
         {vn_pdw.data(), vn_pdw.size() * sizeof(int32_t), 0},
         {vown_tab.data(), vown_tab.size() * sizeof(int32_t), 0},
         {vn_own.data(), vn_own.size() * sizeof(int32_t), 0},
