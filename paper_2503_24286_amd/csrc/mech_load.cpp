@@ -465,8 +465,10 @@ int load_mechanism(const char* path, pyro_mech** out) {
         for (auto& e : part[k]) g_part[e[0]].push_back(k);
     }
     HostSched fw, bw;
-    if (int rc = build_schedule(sin, m->fw_waves, kRxnPerWave, m->fw_waves == kWaves ? kMaxOwn : 16,
-                                kTile * 16, 0.0, g_net, fw)) {
+    // the forward schedule: at most max(8, ceil(S / 8)) species per wave with
+    // 8 wavefronts (16 with 16), ownership weighted by issue order as below
+    const int fw_cap = m->fw_waves == kWaves ? std::max(8, (S + kWaves - 1) / kWaves) : 16;
+    if (int rc = build_schedule(sin, m->fw_waves, kRxnPerWave, fw_cap, kTile * 16, 1.0, g_net, fw)) {
         delete m;
         return rc;
     }
