@@ -21,7 +21,10 @@ imaginary axis for complex-step derivatives.
 Readings of passages the paper leaves garbled or silent are listed in the
 docstrings of the functions that take them.  Every function is pinned by the
 "not gpu" tests (closed forms, invariants, quadrature, complex step vs. finite
-differences, detailed balance, conservation); none is parity unpinned.
+differences, detailed balance, conservation, hand-evaluated third-body and Troe
+values with distinct efficiencies and a finite reduced pressure).  What no pin
+can fix is the agreement of the third-body and Troe conventions with other
+kinetics packages: the paper names these forms without writing them.
 """
 
 from . import eos, kinetics, mechfile, newton, thermo, gradients  # noqa: F401

@@ -321,6 +321,101 @@ def test_troe_special_cases(tmp_path):
                                rtol=1e-13)
 
 
+def test_troe_hand_evaluated_values(tmp_path):
+    """F_cent = 1/2 (alpha = 1, T* = T/ln 2, T*** and T** huge), evaluated by
+    hand: log10 F_cent = -0.30102999566398120, c = -0.4 - 0.67 log10 F_cent =
+    -0.19830990290513262, n = 0.75 - 1.27 log10 F_cent = 1.1323080944932562,
+    d = 0.14.  At x = log10 P_r + c = 1: f1 = 1/(n - d) = 1.0077515295394943 and
+    F = 2^(-1/(1 + f1^2)) = 0.70900157806297...; at x = -2: f1 = -2/(n + 2d) =
+    -1.4161216010856406, F = 0.79403011576779...  The pole of f1 at x = n/d
+    gives F = 1, and f1 = +-1 at x = n/(1 + d) and x = -n/(1 - d) gives
+    F = sqrt(F_cent): both place n and d independently of the centre value."""
+    big = 1e300
+    T = np.array([900.0])
+    troe = (1.0, big, 900.0 / np.log(2.0), big)
+    c = -0.19830990290513262
+    n = 1.1323080944932562
+    for x, F_hand in ((1.0, 0.709001578062973), (-2.0, 0.794030115767798)):
+        Pr = np.array([10.0 ** (x - c)])
+        np.testing.assert_allclose(kinetics.troe_factor(troe, T, Pr), F_hand, rtol=1e-13)
+    # next to the pole of f1 the factor is one
+    Pr = np.array([10.0 ** (n / 0.14 * (1 - 1e-9) - c)])
+    assert abs(kinetics.troe_factor(troe, T, Pr)[0] - 1.0) <= 1e-12
+    for x in (n / 1.14, -n / 0.86):
+        F = kinetics.troe_factor(troe, T, np.array([10.0 ** (x - c)]))
+        np.testing.assert_allclose(F, np.sqrt(0.5), rtol=1e-12)
+    # the same factor inside a falloff rate coefficient: k = k_inf Pr/(1+Pr) F
+    Y = np.array([[0.2], [0.3], [0.5]])
+    rho = 1.6                                  # W = 1: [M] = rho sum Y = 1.6
+    Pr = 10.0 ** (1.0 - c)
+    A0 = Pr * 5.0 / 1.6
+    mt = _falloff_mech(str(tmp_path / "t.pyromech"), 3, 5.0, A0, troe=troe)
+    k, M = kinetics.rate_coefficients(mt, T, rho * Y)
+    np.testing.assert_allclose(M[0], 1.6, rtol=1e-15)
+    np.testing.assert_allclose(k[0], 5.0 * Pr / (1 + Pr) * 0.709001578062973, rtol=1e-13)
+
+
+def _eff_mech(path, eff_a, eff_b, rtype_b=1, A0=None):
+    """A + B + M -> C + M (efficiencies eff_a) and B + C + M -> A + D + M
+    or a falloff B + C -> D (efficiencies eff_b), constant rates."""
+    a = mechs.constant_cp(4, 3.5, 0.0, 20.0)
+    r2 = dict(reac=[(1, 1), (2, 1)], prod=[(0, 1), (3, 1)], type=rtype_b,
+              arrh=(np.log(0.75), 0, 0), eff=eff_b, reversible=False)
+    if rtype_b >= 2:
+        r2.update(prod=[(3, 1)], low=(np.log(A0), 0, 0))
+    return mechs.make(path, W=[1.0] * 4, nasa_low=a, reactions=[
+        dict(reac=[(0, 1), (1, 1)], prod=[(2, 1)], type=1,
+             arrh=(np.log(2.5), 0, 0), eff=eff_a, reversible=False), r2])
+
+
+def test_third_body_efficiencies_hand_evaluated(tmp_path):
+    """Each third-body reaction weights the concentrations with its own
+    efficiency row: q = k C_A C_B (2 C_A + 0.5 C_B + 7 C_C + 3 C_D) for the
+    first reaction and k C_B C_C (4 C_A + 1.5 C_B + 0.25 C_C + 9 C_D) for the
+    second (W = 1 kg/mol, so C = rho Y)."""
+    T = np.array([700.0, 1900.0])
+    Y = np.array([[0.3, 0.05], [0.2, 0.6], [0.4, 0.1], [0.1, 0.25]])
+    rho = np.array([1.7, 0.6])
+    C = rho * Y
+    m = _eff_mech(str(tmp_path / "e.pyromech"), (2.0, 0.5, 7.0, 3.0), (4.0, 1.5, 0.25, 9.0))
+    Rf, Rr, phi, q = kinetics.rates_of_progress(m, rho, T, Y)
+    M1 = 2.0 * C[0] + 0.5 * C[1] + 7.0 * C[2] + 3.0 * C[3]
+    M2 = 4.0 * C[0] + 1.5 * C[1] + 0.25 * C[2] + 9.0 * C[3]
+    np.testing.assert_allclose(q[0], 2.5 * C[0] * C[1] * M1, rtol=1e-15)
+    np.testing.assert_allclose(q[1], 0.75 * C[1] * C[2] * M2, rtol=1e-15)
+    w = kinetics.net_production_rates(m, rho, T, Y)
+    np.testing.assert_allclose(w[2], 2.5 * C[0] * C[1] * M1 - 0.75 * C[1] * C[2] * M2,
+                               rtol=1e-14)
+    np.testing.assert_allclose(w[3], 0.75 * C[1] * C[2] * M2, rtol=1e-15)
+
+
+@pytest.mark.parametrize("rtype", [2, 3])
+def test_falloff_efficiencies_hand_evaluated(tmp_path, rtype):
+    """Falloff B + C (+M) -> D: P_r = k0 [M]/k_inf with [M] = 4 C_A + 1.5 C_B
+    + 0.25 C_C + 9 C_D; Lindemann k = k_inf P_r/(1 + P_r); Troe with F_cent = 1
+    (alpha = 0, T*** and T** huge) gives the same; [M] does not multiply q."""
+    T = np.array([900.0, 1500.0])
+    Y = np.array([[0.3, 0.05], [0.2, 0.6], [0.4, 0.1], [0.1, 0.25]])
+    rho = np.array([1.7, 0.6])
+    C = rho * Y
+    A0 = 3.0
+    m = _eff_mech(str(tmp_path / "f.pyromech"), (2.0, 0.5, 7.0, 3.0),
+                  (4.0, 1.5, 0.25, 9.0), rtype_b=rtype, A0=A0)
+    if rtype == 3:
+        big = 1e300
+        m = mechs.make(str(tmp_path / "f3.pyromech"), W=m.W,
+                       nasa_low=mechs.constant_cp(4, 3.5, 0.0, 20.0),
+                       reactions=[dict(reac=[(1, 1), (2, 1)], prod=[(3, 1)], type=3,
+                                       arrh=(np.log(0.75), 0, 0), low=(np.log(A0), 0, 0),
+                                       troe=(0.0, big, 100.0, big),
+                                       eff=(4.0, 1.5, 0.25, 9.0), reversible=False)])
+    Rf, Rr, phi, q = kinetics.rates_of_progress(m, rho, T, Y)
+    M = 4.0 * C[0] + 1.5 * C[1] + 0.25 * C[2] + 9.0 * C[3]
+    Pr = A0 * M / 0.75
+    j = m.R - 1
+    np.testing.assert_allclose(q[j], 0.75 * Pr / (1 + Pr) * C[1] * C[2], rtol=1e-14)
+
+
 # ---------------------------------------------------------------- Newton
 
 @pytest.mark.parametrize("cfg", [0, 1])
