@@ -27,5 +27,5 @@ can fix is the agreement of the third-body and Troe conventions with other
 kinetics packages: the paper names these forms without writing them.
 """
 
-from . import eos, kinetics, mechfile, newton, thermo, gradients  # noqa: F401
+from . import eos, kinetics, mechfile, newton, thermo, gradients, jacobian, primitive  # noqa: F401
 from .constants import GAS_CONSTANT, ONE_ATM  # noqa: F401

@@ -14,7 +14,19 @@ import numpy as np
 from . import thermo
 
 
+def temperature_from_enthalpy(mech, h, Y, T_guess, rtol=1e-12, max_iter=50):
+    """The same iteration on the enthalpy: T <- T - (Y.h(T) - h)/c_p(T) (the
+    enthalpy variant the paper names at the end of Sec. A.3.1)."""
+    return _newton(mech, h, Y, T_guess, rtol, max_iter, thermo.mixture_enthalpy,
+                   thermo.mixture_cp)
+
+
 def temperature(mech, e, Y, T_guess, rtol=1e-12, max_iter=50):
+    return _newton(mech, e, Y, T_guess, rtol, max_iter, thermo.mixture_internal_energy,
+                   thermo.mixture_cv)
+
+
+def _newton(mech, e, Y, T_guess, rtol, max_iter, value, slope):
     e = np.asarray(e, dtype=float)
     n = e.shape[0]
     T = np.broadcast_to(np.asarray(T_guess, dtype=float), (n,)).copy()
@@ -26,8 +38,8 @@ def temperature(mech, e, Y, T_guess, rtol=1e-12, max_iter=50):
         idx = np.nonzero(active)[0]
         Ti = T[idx]
         Yi = Y[:, idx]
-        resid = thermo.mixture_internal_energy(mech, Ti, Yi) - e[idx]
-        dT = -resid / thermo.mixture_cv(mech, Ti, Yi)
+        resid = value(mech, Ti, Yi) - e[idx]
+        dT = -resid / slope(mech, Ti, Yi)
         Tn = Ti + dT
         T[idx] = Tn
         done = np.abs(dT) <= rtol * np.abs(Tn)

@@ -103,3 +103,27 @@ def mixture_cv(mech, T, Y):
     for k in range(mech.S):
         total = total + Y[k] * cvk[k]
     return total
+
+
+def species_enthalpy(mech, T):
+    """h_k/W_k in J/kg (eq. nasa_poly), (S, n)."""
+    T = np.asarray(T)
+    return species_h_RT(mech, T) * GAS_CONSTANT * T / mech.W[:, None]
+
+
+def mixture_enthalpy(mech, T, Y):
+    """h = sum_k Y_k h_k/W_k, summed in species order."""
+    hk = species_enthalpy(mech, T)
+    total = np.zeros(np.broadcast(np.asarray(T), Y[0]).shape, dtype=np.result_type(hk, Y))
+    for k in range(mech.S):
+        total = total + Y[k] * hk[k]
+    return total
+
+
+def mixture_cp(mech, T, Y):
+    """c_p = sum_k Y_k cp_k/W_k = dh/dT (mass basis)."""
+    cpk = species_cp_R(mech, T) * GAS_CONSTANT / mech.W[:, None]
+    total = np.zeros(np.broadcast(np.asarray(T), Y[0]).shape, dtype=np.result_type(cpk, Y))
+    for k in range(mech.S):
+        total = total + Y[k] * cpk[k]
+    return total
