@@ -85,42 +85,83 @@ def wdot_bytes_per_cell(gm):
     return 8 * (2 + 2 * gm.n_species)
 
 
-def cpu_baseline(n_fwd, n_vjp, cfg=1):
-    """The oracle (NumPy, one thread for its elementwise work) on the first
-    cells of the same workload: Newton from 1200 K and omega on ``n_fwd``
-    cells, the complex-step gradients on ``n_vjp`` cells; the per-cell times
-    add up to one step."""
+def _oracle_chunk(task):
+    """One worker's share of the CPU baseline: draws its cells (untimed), then
+    times the oracle on them.  Returns (seconds of Newton + omega, cells,
+    seconds of the complex-step VJP, cells)."""
+    first_fwd, n_fwd, first_vjp, n_vjp, cfg = task
     import numpy as np
+    from threadpoolctl import threadpool_limits
+
     from oracle import eos, gradients, kinetics, mechfile, newton, thermo
     from pyro_synth.states import draw_cotangent, draw_states
-    m = mechfile.load(MECH)
-    chunk = 8192
-    t_fwd = 0.0
-    done = 0
-    while done < n_fwd:
-        k = min(chunk, n_fwd - done)
-        T, p, Y = draw_states(cfg, k, m.S, first=done)
+    with threadpool_limits(1):
+        m = mechfile.load(MECH)
+        T, p, Y = draw_states(cfg, n_fwd, m.S, first=first_fwd)
         rho = eos.density(m, p, T, Y)
         e = thermo.mixture_internal_energy(m, T, Y)
         t0 = time.perf_counter()
         Tn, st = newton.temperature(m, e, Y, 1200.0)
         w = kinetics.net_production_rates(m, rho, Tn, Y)
-        t_fwd += time.perf_counter() - t0
+        t_fwd = time.perf_counter() - t0
         assert np.isfinite(w).all()
-        done += k
-    T, p, Y = draw_states(cfg, n_vjp, m.S)
-    rho = eos.density(m, p, T, Y)
-    wbar = draw_cotangent(2, n_vjp, m.S)
-    t0 = time.perf_counter()
-    gradients.vjp(m, rho, T, Y, wbar)
-    t_vjp = time.perf_counter() - t0
-    per_cell = t_fwd / n_fwd + t_vjp / n_vjp
-    return {"value": round(1e-6 / per_cell, 6), "unit": "Mcells/s", "cores": 1,
-            "kind": "oracle",
-            "sample": f"first cells of the 2^22-cell workload: Newton + omega on {n_fwd} "
-                      f"cells ({t_fwd:.1f} s), complex-step VJP on {n_vjp} cells "
-                      f"({t_vjp:.1f} s); NumPy oracle, one thread; host "
-                      f"{platform.processor() or platform.machine()}"}
+        T, p, Y = draw_states(cfg, n_vjp, m.S, first=first_vjp)
+        rho = eos.density(m, p, T, Y)
+        wbar = draw_cotangent(2, first_vjp + n_vjp, m.S)[:, first_vjp:]
+        t0 = time.perf_counter()
+        gradients.vjp(m, rho, T, Y, wbar)
+        t_vjp = time.perf_counter() - t0
+    return t_fwd, n_fwd, t_vjp, n_vjp
+
+
+def host_cores():
+    """Cores this process may run on, capped at the 16 a one-GPU share of
+    the host provides."""
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    return max(1, min(16, avail))
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
+
+
+def cpu_baseline(n_fwd_per_core, n_vjp_per_core, cfg=1, cores=None):
+    """The oracle (NumPy, each worker one thread) on consecutive cells of the
+    same workload, one forked worker process per host core: Newton from
+    1200 K and omega on ``n_fwd_per_core`` cells per worker, the complex-step
+    gradients on ``n_vjp_per_core`` cells per worker.  The parallel rate is
+    the total cells over the slowest worker's time, per part; the parts' per-
+    cell times add up to one step.  The same per-worker sample run alone
+    gives the one-thread rate.  Must run before the GPU is touched (workers
+    are forked)."""
+    import multiprocessing as mp
+    cores = cores or host_cores()
+    tasks = [(i * n_fwd_per_core, n_fwd_per_core, i * n_vjp_per_core, n_vjp_per_core, cfg)
+             for i in range(cores)]
+    with mp.get_context("fork").Pool(cores) as pool:
+        res = pool.map(_oracle_chunk, tasks, chunksize=1)
+    t_fwd = max(r[0] for r in res)
+    t_vjp = max(r[2] for r in res)
+    rate = 1e-6 / (t_fwd / (cores * n_fwd_per_core) + t_vjp / (cores * n_vjp_per_core))
+    one = _oracle_chunk(tasks[0])
+    rate1 = 1e-6 / (one[0] / one[1] + one[2] / one[3])
+    return {"value": round(rate, 6), "unit": "Mcells/s", "cores": cores,
+            "kind": "oracle", "one_thread_value": round(rate1, 6),
+            "host": {"nproc": os.cpu_count(), "cores_used": cores, "cpu_model": cpu_model()},
+            "sample": f"consecutive cells of the 2^22-cell workload, {cores} worker processes "
+                      f"of one thread each: Newton + omega on {cores} x {n_fwd_per_core} cells "
+                      f"({t_fwd:.1f} s wall), complex-step VJP on {cores} x {n_vjp_per_core} "
+                      f"cells ({t_vjp:.1f} s wall); one worker alone: {one[0]:.1f} s + "
+                      f"{one[2]:.1f} s"}
 
 
 TRAFFIC_PROFILE = os.path.join(REPO, "profiles", "traffic_cfg1_2e22.md")
@@ -328,8 +369,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cells", type=int, default=1 << 22)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=1 << 19,
-                    help="cells for the oracle's Newton + omega (the VJP uses 1/64 of them)")
+    ap.add_argument("--cpu-sample", type=int, default=1 << 16,
+                    help="cells per host core for the oracle's Newton + omega (the VJP uses "
+                         "1/64 of them)")
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--no-large", action="store_true",
                     help="skip the 160-species mechanism's production-rate line")
@@ -352,6 +394,13 @@ def main():
               "would each run this same per-GPU workload on their own share; "
               "this benchmark runs one GPU only.", file=sys.stderr)
         sys.exit(2)
+
+    # the oracle's workers are forked before anything touches the GPU
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(args.cpu_sample, max(args.cpu_sample // 64, 16))
+        print(f"# cpu baseline: {cpu['value']} Mcells/s on {cpu['cores']} cores",
+              file=sys.stderr, flush=True)
 
     import numpy as np
     import torch
@@ -492,8 +541,8 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    if not args.no_cpu_baseline:
-        result["cpu_baseline"] = cpu_baseline(args.cpu_sample, max(args.cpu_sample // 64, 64))
+    if cpu is not None:
+        result["cpu_baseline"] = cpu
     print(json.dumps(result), flush=True)
 
 
