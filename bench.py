@@ -208,6 +208,68 @@ def _time_ms(fn, reps, stream):
     return a.elapsed_time(b) / reps
 
 
+def fp32_leg(gm, rho, T, Y, stream, reps):
+    """The FP32 production rates (log-space form in float) on the same cells:
+    time, the fraction of cells with a non-finite result (a rate beyond the
+    float range), and the per-cell normwise error of the finite ones against
+    the FP64 kernel on the same float-rounded inputs (the FP64 kernel matches
+    the oracle to 1e-12)."""
+    import numpy as np
+    import torch
+
+    import paper_2503_24286_amd as pyro
+    r32, t32, y32 = rho.float(), T.float(), Y.float()
+    w32 = torch.empty_like(y32)
+    ms = _time_ms(lambda: pyro.production_rates(gm, r32, t32, y32, out=w32), reps, stream)
+    w64 = pyro.production_rates(gm, r32.double(), t32.double(), y32.double())
+    finite = torch.isfinite(w32).all(dim=0)
+    diff = torch.linalg.vector_norm(w32.double() - w64, dim=0)
+    ref = torch.linalg.vector_norm(w64, dim=0)
+    err = (diff / torch.where(ref > 0, ref, torch.ones_like(ref)))[finite].cpu().numpy()
+    over = 1.0 - float(finite.double().mean())
+    n = Y.shape[1]
+    del r32, t32, y32, w32, w64
+    q = lambda x: float(np.quantile(err, x)) if err.size else None  # noqa: E731
+    return {"ms": round(ms, 4), "Mcells_s": round(n / (ms * 1e-3) / 1e6, 3),
+            "overflow_fraction": round(over, 6),
+            "normwise_err_vs_fp64": {"p50": q(0.5), "p99": q(0.99), "p99.9": q(0.999),
+                                     "max": float(err.max()) if err.size else None},
+            "note": "log-space form in float; overflowing cells have a rate beyond the float "
+                    "range (config-1 rates reach ~1e69)"}
+
+
+def jacobian_leg(args, log):
+    """The chemical Jacobian dS/dY at fixed density and energy on the first
+    ``--jacobian-cells`` cells of the same workload (S reverse sweeps with a
+    unit cotangent per row): time and throughput."""
+    import numpy as np
+    import torch
+
+    import paper_2503_24286_amd as pyro
+    from pyro_synth.states import draw_states
+    gm = pyro.Mechanism(MECH)
+    n = args.jacobian_cells
+    T, p, Y = draw_states(1, n, gm.n_species)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
+    T_d, p_d, Y_d = dev(T), dev(p), dev(Y)
+    rho = pyro.density(gm, p_d, T_d, Y_d)
+    S = gm.n_species
+    J = torch.empty((S, S, n), dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+    ms = _time_ms(lambda: pyro.chemical_jacobian(gm, rho, T_d, Y_d, out=J), 3, stream)
+    ok = bool(torch.isfinite(J).all())
+    del J
+    gm.close()
+    torch.cuda.empty_cache()
+    log(f"jacobian: {n} cells in {ms:.2f} ms")
+    out_bytes = 8 * S * S + 8 * (2 + S)
+    return {"workload": f"53-species mechanism, {n} cells, fixed density and internal energy",
+            "ms": round(ms, 3), "Mcells_s": round(n / (ms * 1e-3) / 1e6, 3), "finite": ok,
+            "hbm_GBps_compulsory": round(out_bytes * n / (ms * 1e-3) / 1e9, 1),
+            "method": "S reverse sweeps, unit cotangent W_j on species j per row; reactions "
+                      "without species j skipped"}
+
+
 def large_mechanism_leg(args, log):
     """The 160-species, 900-reaction mechanism (2^20 cells, states drawn as
     for the 53-species workload): production rates alone, with the kernel
@@ -373,6 +435,8 @@ def main():
                     help="cells per host core for the oracle's Newton + omega (the VJP uses "
                          "1/64 of them)")
     ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--no-jacobian", action="store_true")
+    ap.add_argument("--jacobian-cells", type=int, default=1 << 18)
     ap.add_argument("--no-large", action="store_true",
                     help="skip the 160-species mechanism's production-rate line")
     ap.add_argument("--train-states", type=int, default=1 << 24)
@@ -475,12 +539,16 @@ def main():
                     ("third_body_and_net_rates_on_mfma", default_variant
                      | _lib.PYRO_WDOT_MFMA_THIRD_BODY | _lib.PYRO_WDOT_MFMA_NET_RATES),
                     ("reaction_equilibrium_third_body_on_mfma",
-                     _lib.PYRO_WDOT_REACTION_EQUILIBRIUM | _lib.PYRO_WDOT_MFMA_THIRD_BODY)):
+                     _lib.PYRO_WDOT_REACTION_EQUILIBRIUM | _lib.PYRO_WDOT_MFMA_THIRD_BODY),
+                    ("log_space", _lib.PYRO_WDOT_LOG_SPACE)):
         gm.wdot_variant = v
         variant_ms[name] = round(_time_ms(
             lambda: pyro.production_rates(gm, rho, T_out, Y_d, out=w2), 3, stream), 4)
     gm.wdot_variant = default_variant
     del w2
+    fp32 = fp32_leg(gm, rho, T_out, Y_d, stream, max(args.steps, 3))
+    print(f"# fp32: {fp32['ms']} ms, {fp32['overflow_fraction']:.4f} of the cells overflow",
+          file=sys.stderr, flush=True)
 
     ms_per_step = total_ms / args.steps
     value = n / (ms_per_step * 1e-3) / 1e6
@@ -523,14 +591,17 @@ def main():
                        "wdot_variants_outside_step": variant_ms},
         "roofline": roof("vjp_kernel", fused_ms, fused_flops_per_cell(gm),
                          fused_bytes_per_cell(gm)),
-        "roofline_other": roof("wdot_f64_kernel", wdot_ms, wdot_flops_per_cell(gm),
+        "roofline_other": roof("wdot_kernel", wdot_ms, wdot_flops_per_cell(gm),
                                wdot_bytes_per_cell(gm)),
+        "fp32": fp32,
     }
     gm.close()
     del T_d, p_d, Y_d, rho, e, T_out, status, w, wbar, Ybar, Tbar, pbar
     torch.cuda.empty_cache()
     def log(msg):
         print(f"# {msg}", file=sys.stderr, flush=True)
+    if not args.no_jacobian:
+        result["jacobian"] = jacobian_leg(args, log)
     if not args.no_large:
         result["large_mechanism"] = large_mechanism_leg(args, log)
     if not args.no_surrogate:

@@ -82,7 +82,15 @@ enum pyro_wdot_variant {
      * the FP64 matrix cores over the reaction chunks with the dense nu
      * (v_mfma_f64_16x16x4f64), instead of the sparse per-species gathering;
      * at most 64 species */
-    PYRO_WDOT_MFMA_NET_RATES = 4
+    PYRO_WDOT_MFMA_NET_RATES = 4,
+    /* log-space form (implies the reaction-equilibrium coefficients, no
+     * matrix-core flags): each rate is one exponential of a sum of logarithms,
+     * R_f = exp(ln k + sum_k nu'_kj ln C_k) and R_r = exp(ln k + dg_j +
+     * dnu_j ln(R T/p0) + sum_k nu''_kj ln C_k) (ln [M] added for third-body
+     * reactions, ln(P_r/(1+P_r)) + ln F for falloff), so no intermediate
+     * overflows before the rate itself; LDS rows hold C and ln C.  Every
+     * PYRO_F32 call uses this form. */
+    PYRO_WDOT_LOG_SPACE = 8
 };
 
 typedef struct pyro_mech pyro_mech;
@@ -122,8 +130,9 @@ PYRO_API void pyro_mech_free(pyro_mech* mech);
 PYRO_API int pyro_mech_get_info(const pyro_mech* mech, pyro_mech_info* info);
 /* Selects the production-rate kernel variant (enum pyro_wdot_variant, an
  * equilibrium variant optionally or-ed with PYRO_WDOT_MFMA_THIRD_BODY and
- * PYRO_WDOT_MFMA_NET_RATES) used by
- * pyro_production_rates and the surrogate's fallback.  The loader picks the
+ * PYRO_WDOT_MFMA_NET_RATES, or PYRO_WDOT_LOG_SPACE, which reads back as
+ * PYRO_WDOT_LOG_SPACE | PYRO_WDOT_REACTION_EQUILIBRIUM) used by FP64
+ * pyro_production_rates calls and the surrogate's fallback.  The loader picks the
  * species variant when its LDS tile fits and the reaction variant otherwise;
  * PYRO_E_UNSUPPORTED if the requested variant cannot run this mechanism.
  * Not thread-safe against concurrent calls on the same handle. */
@@ -147,8 +156,13 @@ PYRO_API int pyro_mech_arrhenius(const pyro_mech* mech, double* params_out);
  *   wdot[S*ld]     output omega_k
  *   params         device array of 3*n_params doubles (ln A, b, Ea) that
  *                  replaces the mechanism's Arrhenius triples, or NULL
- *   dtype          PYRO_F64: rho, T, Y, wdot are double.  PYRO_F32: they are
- *                  float and the arithmetic is float (params stay double).
+ *   dtype          PYRO_F64: rho, T, Y, wdot are double, computed with the
+ *                  mechanism's current variant.  PYRO_F32: they are float and
+ *                  the arithmetic is float, always in the log-space form
+ *                  (params stay double and are rounded to float); a rate
+ *                  beyond the float range gives an infinite or NaN omega
+ *                  (counted by the caller), a smaller one never overflows.
+ *                  PYRO_E_UNSUPPORTED where the log-space form cannot run.
  */
 PYRO_API int pyro_production_rates(const pyro_mech* mech, int64_t n, int64_t ld,
                           int dtype, const void* rho, const void* T,
@@ -186,6 +200,35 @@ PYRO_API int pyro_production_rates_vjp(const pyro_mech* mech, int64_t n, int64_t
                                        double* wdot, const double* params, void* stream);
 
 /*
+ * Chemical Jacobian J = dS/dY of the source terms S_j = W_j omega_j
+ * (eq. jacobian and eq. chem_jacobian, Sec. "Automatic Differentiation
+ * Enables Implicit Time Marching"; eq. massfrac_ode defines S), per cell, at
+ * fixed density.
+ *
+ *   rho[n], T[n], Y[S*ld]  the state (as for pyro_production_rates); with
+ *                  fixed_energy = 1, T must be the temperature of the state's
+ *                  internal energy (as pyro_temperature returns it)
+ *   fixed_energy   1: T follows Y at fixed internal energy (the paper's
+ *                  source-term function, whose temperature comes from the
+ *                  Newton inversion of eq. delta_temp), so that
+ *                  J_jk = dS_j/dY_k|_T - dS_j/dT e_k/c_v with
+ *                  e_k = (h_k - R T)/W_k and c_v = sum_i Y_i c_v,i;
+ *                  0: the partial derivative at fixed T
+ *   J[S*S*ld]      output, J[(j*S + k)*ld + i] = dS_j/dY_k of cell i (rows of
+ *                  S*ld doubles, each species-major like Y); the entries of a
+ *                  column k with Y_k <= 0 have no concentration part
+ *   dSdT           optional output [S*ld], dS_j/dT at fixed Y, or NULL
+ *   params         Arrhenius triples as for pyro_production_rates, or NULL
+ * Asynchronous; S reverse sweeps with a unit cotangent per row (the
+ * reactions without the row's species are skipped).  FP64 only.
+ * PYRO_E_UNSUPPORTED for mechanisms the reverse sweep cannot run.
+ */
+PYRO_API int pyro_chemical_jacobian(const pyro_mech* mech, int64_t n, int64_t ld,
+                                    const double* rho, const double* T, const double* Y,
+                                    int fixed_energy, double* J, double* dSdT,
+                                    const double* params, void* stream);
+
+/*
  * Temperature from the mass-specific internal energy by Newton iteration
  * (Appendix A.3.1: eq. int_energy, eq. delta_temp, eq. cv):
  * T <- T - (Y.e(T) - e)/c_v(T), per cell, until the first update with
@@ -203,6 +246,108 @@ PYRO_API int pyro_temperature(const pyro_mech* mech, int64_t n, int64_t ld,
                      const double* e, const double* Y, const double* T_guess,
                      double T_guess_value, double* T_out, int32_t* status,
                      int max_iter, double rtol, void* stream);
+
+/* Temperature from the mass-specific enthalpy h = sum_k Y_k h_k/W_k (J/kg)
+ * by the same Newton iteration with c_p in place of c_v (the enthalpy
+ * variant named at the end of Appendix A.3.1): T <- T - (Y.h(T) - h)/c_p(T).
+ * Arguments, status and errors as for pyro_temperature. */
+PYRO_API int pyro_temperature_from_enthalpy(const pyro_mech* mech, int64_t n, int64_t ld,
+                                            const double* h, const double* Y,
+                                            const double* T_guess, double T_guess_value,
+                                            double* T_out, int32_t* status, int max_iter,
+                                            double rtol, void* stream);
+
+/*
+ * Primitive from conserved variables, the per-cell equation-of-state routine
+ * of the paper's flow solver (Sec. "Python Code Generation and Immediate
+ * Execution using NumPy", in its order; eq. delta_temp and eq. eos):
+ * rho = sum_k rho_k, Y_k = rho_k/rho, u = m/rho, e = E/rho - |u|^2/2,
+ * T = Newton inversion of e (as pyro_temperature), p = rho R T/W.
+ *
+ *   dim                    0..3 velocity components
+ *   partial_densities[S*ld] rho_k (kg/m^3), species-major
+ *   momentum[dim*ld]       rho u_d, component-major (ignored if dim == 0)
+ *   total_energy[n]        E = rho (e + |u|^2/2) (J/m^3)
+ *   T_guess, T_guess_value, max_iter, rtol, status: as for pyro_temperature
+ *   rho_out[n], Y_out[S*ld], u_out[dim*ld], T_out[n], p_out[n]: outputs
+ * A cell with rho = 0 gives NaN/Inf results (no error).
+ */
+PYRO_API int pyro_primitive_from_conserved(const pyro_mech* mech, int64_t n, int64_t ld,
+                                           int dim, const double* partial_densities,
+                                           const double* momentum, const double* total_energy,
+                                           const double* T_guess, double T_guess_value,
+                                           double* rho_out, double* Y_out, double* u_out,
+                                           double* T_out, double* p_out, int32_t* status,
+                                           int max_iter, double rtol, void* stream);
+
+/*
+ * Mixture-averaged transport (appendix "Extensions to Flow & Transport":
+ * eq. mixavg_viscosity, eq. mixavg_conductivity, eq. species_cond,
+ * eq. diff_mix_rule and the binary-diffusivity fit).  With L = ln T (natural
+ * logarithm) and X_k = W Y_k/W_k (W the mixture molar mass of the Y given,
+ * not renormalised):
+ *   mu_k = sqrt(T) (sum_m b_km L^m)^2, kappa_k = sqrt(T) sum_m c_km L^m,
+ *   D_kj = sqrt(T) sum_m a_kjm L^m (no pressure factor),
+ *   mu = sum_k X_k mu_k / sum_j Phi_kj X_j with
+ *        Phi_kj = (1 + sqrt((mu_k/mu_j) sqrt(W_j/W_k)))^2 / sqrt(8 (1 + W_k/W_j)),
+ *   kappa = (sum_k X_k kappa_k + (sum_k X_k/kappa_k)^-1)/2,
+ *   D_k,m = (W - X_k W_k)/W (sum_{j != k} X_j/D_kj)^-1  (NaN/Inf for a pure
+ *        species, left to IEEE arithmetic).
+ *
+ * pyro_transport_create copies host fits, visc[S][5] (b_km), cond[S][5]
+ * (c_km) and diff[S][S][5] (a_kjm, index k first), into device tables of the
+ * mechanism's device, with the per-pair constants of Phi formed once; *out
+ * owns them until pyro_transport_free.  PYRO_E_ARG for non-finite
+ * coefficients.  pyro_mixture_transport takes T[n], Y[S*ld] (device) and
+ * writes mu[n] (Pa s), kappa[n] (W/(m K)) and D[S*ld] (m^2/s).
+ */
+typedef struct pyro_transport pyro_transport;
+PYRO_API int pyro_transport_create(const pyro_mech* mech, const double* visc,
+                                   const double* cond, const double* diff,
+                                   pyro_transport** out);
+PYRO_API void pyro_transport_free(pyro_transport* tr);
+PYRO_API int pyro_mixture_transport(const pyro_mech* mech, const pyro_transport* tr, int64_t n,
+                                    int64_t ld, const double* T, const double* Y, double* mu,
+                                    double* kappa, double* D, void* stream);
+
+/*
+ * One time step of the homogeneous adiabatic isochoric reactor,
+ * rho dY_k/dt = W_k omega_k (eq. massfrac_ode), at constant density and
+ * internal energy; every evaluation takes T from the Newton inversion of the
+ * energy (eq. delta_temp, rtol 1e-12, at most 50 updates).
+ *
+ *   PYRO_REACTOR_RK4  classical four-stage Runge-Kutta (the paper's explicit
+ *                     autoignition marching);
+ *   PYRO_REACTOR_CN   Crank-Nicolson, F = Y - Y^m - dt/(2 rho) (S + S^m) = 0
+ *                     (eq. crank_nicol_rhs with the density of eq. massfrac_ode)
+ *                     solved by Newton with the matrix I - dt/(2 rho) J
+ *                     (eq. crank_nicol_jac; J = dS/dY at fixed density and
+ *                     energy, as pyro_chemical_jacobian) from Y^m, until the
+ *                     first update with max_k |dY_k| <= tol or max_newton
+ *                     updates; each update solves every cell's S x S system
+ *                     by Gaussian elimination with partial pivoting.  The
+ *                     call waits on the stream after each update to stop once
+ *                     every cell has converged.
+ *
+ *   rho[n], e[n]      density and internal energy (constant over the step)
+ *   Y[S*ld]           in: Y^m; out: the new mass fractions
+ *   T[n]              in: guess for the first inversion; out: T of the new Y
+ *   dt                device [n] step per cell, or NULL to use dt_value
+ *   status[n]         out: RK4, the final inversion's count (0 if an inversion
+ *                     failed on the way); CN, the Newton updates taken,
+ *                     negated if tol was not met
+ *   workspace         device, 256-byte aligned, at least
+ *                     pyro_reactor_workspace_size(mech, n, ld, method) bytes
+ *                     (CN holds one S x S matrix per cell)
+ */
+enum pyro_reactor_method { PYRO_REACTOR_RK4 = 0, PYRO_REACTOR_CN = 1 };
+PYRO_API size_t pyro_reactor_workspace_size(const pyro_mech* mech, int64_t n, int64_t ld,
+                                            int method);
+PYRO_API int pyro_reactor_step(const pyro_mech* mech, int method, int64_t n, int64_t ld,
+                               const double* rho, const double* e, double* Y, double* T,
+                               const double* dt, double dt_value, double tol, int max_newton,
+                               int32_t* status, void* workspace, size_t workspace_bytes,
+                               void* stream);
 
 /* Equation of state (Appendix A.1, eq. eos): rho = p W/(R T) and
  * p = rho R T/W with W = (sum_k Y_k/W_k)^-1.  FP64 cell arrays. */

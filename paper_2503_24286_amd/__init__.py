@@ -6,6 +6,8 @@ include/pyro.h.
 """
 
 from ._lib import PyroError  # noqa: F401
-from .api import (Mechanism, ProductionRates, density, internal_energy,  # noqa: F401
-                  pressure, production_rates, production_rates_autograd,
-                  production_rates_vjp, temperature)
+from .api import (Mechanism, ProductionRates, Transport, chemical_jacobian,  # noqa: F401
+                  density, internal_energy, mixture_transport, pressure,
+                  primitive_from_conserved, production_rates, reactor_step,
+                  production_rates_autograd, production_rates_vjp, temperature,
+                  temperature_from_enthalpy)

@@ -25,6 +25,9 @@ PYRO_WDOT_SPECIES_EQUILIBRIUM = 0
 PYRO_WDOT_REACTION_EQUILIBRIUM = 1
 PYRO_WDOT_MFMA_THIRD_BODY = 2
 PYRO_WDOT_MFMA_NET_RATES = 4
+PYRO_WDOT_LOG_SPACE = 8
+PYRO_REACTOR_RK4 = 0
+PYRO_REACTOR_CN = 1
 
 
 class PyroError(RuntimeError):
@@ -57,6 +60,16 @@ SIGNATURES = {
     "pyro_production_rates": (_I, [_P, _I64, _I64, _I, _P, _P, _P, _P, _P, _P]),
     "pyro_production_rates_vjp": (_I, [_P, _I64, _I64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "pyro_temperature": (_I, [_P, _I64, _I64, _P, _P, _P, _D, _P, _P, _I, _D, _P]),
+    "pyro_chemical_jacobian": (_I, [_P, _I64, _I64, _P, _P, _P, _I, _P, _P, _P, _P]),
+    "pyro_temperature_from_enthalpy": (_I, [_P, _I64, _I64, _P, _P, _P, _D, _P, _P, _I, _D, _P]),
+    "pyro_primitive_from_conserved": (_I, [_P, _I64, _I64, _I, _P, _P, _P, _P, _D, _P, _P, _P,
+                                           _P, _P, _P, _I, _D, _P]),
+    "pyro_reactor_workspace_size": (ctypes.c_size_t, [_P, _I64, _I64, _I]),
+    "pyro_reactor_step": (_I, [_P, _I, _I64, _I64, _P, _P, _P, _P, _P, _D, _D, _I, _P, _P,
+                               ctypes.c_size_t, _P]),
+    "pyro_transport_create": (_I, [_P, _P, _P, _P, ctypes.POINTER(_P)]),
+    "pyro_transport_free": (None, [_P]),
+    "pyro_mixture_transport": (_I, [_P, _P, _I64, _I64, _P, _P, _P, _P, _P, _P]),
     "pyro_density": (_I, [_P, _I64, _I64, _P, _P, _P, _P, _P]),
     "pyro_pressure": (_I, [_P, _I64, _I64, _P, _P, _P, _P, _P]),
     "pyro_internal_energy": (_I, [_P, _I64, _I64, _P, _P, _P, _P]),
@@ -102,7 +115,11 @@ def lib():
                 "(there is no CPU fallback)")
         handle = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in SIGNATURES.items():
-            fn = getattr(handle, name)
+            # a symbol this build of the library lacks stays unbound: calling
+            # it raises AttributeError, the other entry points still work
+            fn = getattr(handle, name, None)
+            if fn is None:
+                continue
             fn.restype = res
             fn.argtypes = args
         _lib = handle

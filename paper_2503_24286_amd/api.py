@@ -141,6 +141,144 @@ def temperature(mech, e, Y, T_guess=1200.0, max_iter=50, rtol=1e-12, out=None, s
     return out, status
 
 
+def temperature_from_enthalpy(mech, h, Y, T_guess=1200.0, max_iter=50, rtol=1e-12, out=None,
+                              status=None):
+    """Newton inversion T(h, Y) from the mass-specific enthalpy; returns
+    (T, status)."""
+    S = mech.n_species
+    n = Y.shape[1]
+    ld = _species_major(Y, S, torch.float64, "Y")
+    _cells(h, n, torch.float64, "h")
+    tg = None
+    tg_value = 0.0
+    if isinstance(T_guess, torch.Tensor):
+        _cells(T_guess, n, torch.float64, "T_guess")
+        tg = T_guess
+    else:
+        tg_value = float(T_guess)
+    if out is None:
+        out = torch.empty(n, dtype=torch.float64, device=Y.device)
+    if status is None:
+        status = torch.empty(n, dtype=torch.int32, device=Y.device)
+    check(lib().pyro_temperature_from_enthalpy(mech.handle, n, ld, _ptr(h), _ptr(Y), _ptr(tg),
+                                               tg_value, _ptr(out), _ptr(status), int(max_iter),
+                                               float(rtol), _stream(Y.device)))
+    return out, status
+
+
+def primitive_from_conserved(mech, partial_densities, momentum, total_energy, T_guess=1200.0,
+                             max_iter=50, rtol=1e-12):
+    """(rho, Y, u, T, p, status) from the partial densities (S, n), the
+    momentum (dim, n) with the row stride of the densities (or None) and the
+    total energy (n,)."""
+    S = mech.n_species
+    n = partial_densities.shape[1]
+    ld = _species_major(partial_densities, S, torch.float64, "partial_densities")
+    _cells(total_energy, n, torch.float64, "total_energy")
+    dim = 0 if momentum is None else momentum.shape[0]
+    if dim:
+        if (momentum.dim() != 2 or momentum.shape[1] != n or momentum.dtype != torch.float64
+                or not momentum.is_cuda or momentum.stride(1) != 1
+                or (dim > 1 and momentum.stride(0) != ld)):
+            raise ValueError("momentum must be a (dim, n) float64 view with the row stride "
+                             "of the densities")
+    tg = None
+    tg_value = 0.0
+    if isinstance(T_guess, torch.Tensor):
+        _cells(T_guess, n, torch.float64, "T_guess")
+        tg = T_guess
+    else:
+        tg_value = float(T_guess)
+    dev = partial_densities.device
+    rho = torch.empty(n, dtype=torch.float64, device=dev)
+    Y = torch.empty((S, ld), dtype=torch.float64, device=dev)[:, :n]
+    u = torch.empty((max(dim, 1), ld), dtype=torch.float64, device=dev)[:dim, :n]
+    T = torch.empty(n, dtype=torch.float64, device=dev)
+    p = torch.empty(n, dtype=torch.float64, device=dev)
+    status = torch.empty(n, dtype=torch.int32, device=dev)
+    check(lib().pyro_primitive_from_conserved(
+        mech.handle, n, ld, dim, _ptr(partial_densities), _ptr(momentum if dim else None),
+        _ptr(total_energy), _ptr(tg), tg_value, _ptr(rho), _ptr(Y), _ptr(u if dim else None),
+        _ptr(T), _ptr(p), _ptr(status), int(max_iter), float(rtol), _stream(dev)))
+    return rho, Y, u, T, p, status
+
+
+def reactor_step(mech, method, rho, e, Y, T, dt, tol=1e-12, max_newton=20, status=None):
+    """One reactor step in place on Y (S, n) and T (n,): ``method`` "rk4" or
+    "cn"; dt a float or an (n,) tensor.  Returns status (n,) int32."""
+    S = mech.n_species
+    n = Y.shape[1]
+    ld = _species_major(Y, S, torch.float64, "Y")
+    _cells(rho, n, torch.float64, "rho")
+    _cells(e, n, torch.float64, "e")
+    _cells(T, n, torch.float64, "T")
+    code = {"rk4": _lib.PYRO_REACTOR_RK4, "cn": _lib.PYRO_REACTOR_CN}[method]
+    dtp, dtv = None, 0.0
+    if isinstance(dt, torch.Tensor):
+        _cells(dt, n, torch.float64, "dt")
+        dtp = dt
+    else:
+        dtv = float(dt)
+    if status is None:
+        status = torch.empty(n, dtype=torch.int32, device=Y.device)
+    size = lib().pyro_reactor_workspace_size(mech.handle, n, ld, code)
+    ws = torch.empty(max(size, 1) + 256, dtype=torch.uint8, device=Y.device)
+    off = (-ws.data_ptr()) % 256
+    check(lib().pyro_reactor_step(mech.handle, code, n, ld, _ptr(rho), _ptr(e), _ptr(Y), _ptr(T),
+                                  _ptr(dtp), dtv, float(tol), int(max_newton), _ptr(status),
+                                  ctypes.c_void_p(ws.data_ptr() + off), size, _stream(Y.device)))
+    return status
+
+
+class Transport:
+    """Device tables of a set of transport fits for a mechanism
+    (``pyro_transport_create``): visc (S, 5), cond (S, 5), diff (S, S, 5)."""
+
+    def __init__(self, mech, visc, cond, diff):
+        S = mech.n_species
+        visc = np.ascontiguousarray(visc, dtype=np.float64)
+        cond = np.ascontiguousarray(cond, dtype=np.float64)
+        diff = np.ascontiguousarray(diff, dtype=np.float64)
+        if visc.shape != (S, 5) or cond.shape != (S, 5) or diff.shape != (S, S, 5):
+            raise ValueError("fits must have shapes (S, 5), (S, 5) and (S, S, 5)")
+        handle = ctypes.c_void_p()
+        vp = ctypes.c_void_p
+        check(lib().pyro_transport_create(mech.handle, visc.ctypes.data_as(vp),
+                                          cond.ctypes.data_as(vp), diff.ctypes.data_as(vp),
+                                          ctypes.byref(handle)))
+        self._h = handle
+        self.mech = mech
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().pyro_transport_free(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def mixture_transport(mech, tr, T, Y):
+    """(mu (n,), kappa (n,), D (S, n)) of the mixture-averaged model."""
+    S = mech.n_species
+    n = Y.shape[1]
+    ld = _species_major(Y, S, torch.float64, "Y")
+    _cells(T, n, torch.float64, "T")
+    mu = torch.empty(n, dtype=torch.float64, device=Y.device)
+    kappa = torch.empty(n, dtype=torch.float64, device=Y.device)
+    D = torch.empty((S, ld), dtype=torch.float64, device=Y.device)[:, :n]
+    check(lib().pyro_mixture_transport(mech.handle, tr.handle, n, ld, _ptr(T), _ptr(Y), _ptr(mu),
+                                       _ptr(kappa), _ptr(D), _stream(Y.device)))
+    return mu, kappa, D
+
+
 def density(mech, p, T, Y, out=None):
     S = mech.n_species
     n = Y.shape[1]
@@ -210,6 +348,33 @@ def production_rates_vjp(mech, rho, T, Y, wbar, params=None, Ybar=None, Tbar=Non
         mech.handle, n, ld, _ptr(rho), _ptr(T), _ptr(Y), _ptr(wbar), _ptr(Ybar), _ptr(Tbar),
         _ptr(params_bar), _ptr(wdot), _ptr(params), _stream(Y.device)))
     return Ybar, Tbar, params_bar
+
+
+def chemical_jacobian(mech, rho, T, Y, fixed_energy=True, params=None, out=None, dSdT=None):
+    """J (S, S, n) with J[j, k] = dS_j/dY_k, S_j = W_j omega_j, at fixed
+    density and (default) fixed internal energy, T being the state's
+    temperature.  ``out`` may be an (S, S, n) view whose innermost rows have
+    the row stride of Y; ``dSdT`` an (S, n) view with that stride."""
+    S = mech.n_species
+    n = Y.shape[1]
+    ld = _species_major(Y, S, torch.float64, "Y")
+    _cells(rho, n, torch.float64, "rho")
+    _cells(T, n, torch.float64, "T")
+    if out is None:
+        out = torch.empty((S, S, ld), dtype=torch.float64, device=Y.device)[:, :, :n]
+    if (out.shape != (S, S, n) or out.dtype != torch.float64 or not out.is_cuda
+            or out.stride() != (S * ld, ld, 1)):
+        raise ValueError("out must be an (S, S, n) float64 view with strides (S*ld, ld, 1)")
+    if dSdT is not None and _species_major(dSdT, S, torch.float64, "dSdT") != ld:
+        raise ValueError("dSdT must have the row stride of Y")
+    if params is not None:
+        if params.dtype != torch.float64 or params.numel() != 3 * mech.n_params:
+            raise ValueError("params must hold 3*n_params float64 values")
+        params = params.contiguous()
+    check(lib().pyro_chemical_jacobian(mech.handle, n, ld, _ptr(rho), _ptr(T), _ptr(Y),
+                                       1 if fixed_energy else 0, _ptr(out), _ptr(dSdT),
+                                       _ptr(params), _stream(Y.device)))
+    return out
 
 
 class ProductionRates(torch.autograd.Function):

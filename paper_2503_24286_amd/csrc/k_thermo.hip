@@ -49,8 +49,22 @@ __device__ inline void fold(const DevMech& m, const double* __restrict__ Y, int6
     }
 }
 
-// e(T)/R and c_v(T)/R of the folded mixture.
+// Divides the folded coefficients by d (a fold over partial densities
+// rho_k then gives the fold over Y_k = rho_k/rho).
 template <int NG>
+__device__ inline void scale(Mixture& mx, double d) {
+#pragma unroll
+    for (int g = 0; g < NG; ++g)
+#pragma unroll
+        for (int r = 0; r < 2; ++r)
+#pragma unroll
+            for (int q = 0; q < 6; ++q) mx.A[g][r][q] /= d;
+    mx.xsum /= d;
+}
+
+// e(T)/R and c_v(T)/R of the folded mixture, or with ENTHALPY h(T)/R and
+// c_p(T)/R (the same sums without the -R T and -R per mole of species).
+template <int NG, bool ENTHALPY = false>
 __device__ inline void energy(const DevMech& m, const Mixture& mx, double T, double& e_R,
                               double& cv_R) {
     double h = 0.0, cp = 0.0;
@@ -64,11 +78,43 @@ __device__ inline void energy(const DevMech& m, const Mixture& mx, double T, dou
                               T * (a[3] * 0.25 + T * (a[4] * 0.2)))));
         cp += a[0] + T * (a[1] + T * (a[2] + T * (a[3] + T * a[4])));
     }
-    e_R = h - T * mx.xsum;
-    cv_R = cp - mx.xsum;
+    if constexpr (ENTHALPY) {
+        e_R = h;
+        cv_R = cp;
+    } else {
+        e_R = h - T * mx.xsum;
+        cv_R = cp - mx.xsum;
+    }
 }
 
-template <int NG>
+// Newton updates T <- T - (value(T) - target)/slope(T) until the first
+// update with |dT| <= rtol |T| (status = updates taken) or max_iter updates
+// (status = -max_iter); the loop runs while any lane of the wave is active.
+template <int NG, bool ENTHALPY>
+__device__ inline double newton_solve(const DevMech& m, const Mixture& mx, double target_R,
+                                      double T, bool valid, int max_iter, double rtol,
+                                      int32_t& st) {
+    st = -max_iter;
+    bool active = valid;
+    for (int it = 0; it < max_iter; ++it) {
+        if (!__any(active)) break;
+        if (active) {
+            double eR, cvR;
+            energy<NG, ENTHALPY>(m, mx, T, eR, cvR);
+            const double dT = -(eR - target_R) / cvR;
+            T += dT;
+            if (fabs(dT) <= rtol * fabs(T)) {
+                st = it + 1;
+                active = false;
+            }
+        }
+    }
+    return T;
+}
+
+// ENTHALPY: the target is the mass-specific enthalpy (the variant closing
+// Sec. A.3.1), else the internal energy (eq. delta_temp).
+template <int NG, bool ENTHALPY>
 __global__ __launch_bounds__(kBlock) void newton_kernel(
     DevMech m, int64_t n, int64_t ld, const double* __restrict__ e,
     const double* __restrict__ Y, const double* __restrict__ Tg, double Tg_value,
@@ -78,27 +124,53 @@ __global__ __launch_bounds__(kBlock) void newton_kernel(
     const int64_t c = valid ? i : n - 1;
     Mixture mx;
     fold<NG>(m, Y, ld, c, mx);
-    const double target = e[c] * (1.0 / kGasConstant);
-    double T = Tg ? Tg[c] : Tg_value;
-    int32_t st = -max_iter;
-    bool active = valid;
-    for (int it = 0; it < max_iter; ++it) {
-        if (!__any(active)) break;
-        if (active) {
-            double eR, cvR;
-            energy<NG>(m, mx, T, eR, cvR);
-            const double dT = -(eR - target) / cvR;
-            T += dT;
-            if (fabs(dT) <= rtol * fabs(T)) {
-                st = it + 1;
-                active = false;
-            }
-        }
-    }
+    int32_t st;
+    const double T = newton_solve<NG, ENTHALPY>(m, mx, e[c] * (1.0 / kGasConstant),
+                                                Tg ? Tg[c] : Tg_value, valid, max_iter, rtol, st);
     if (valid) {
         T_out[i] = T;
         status[i] = st;
     }
+}
+
+// Primitive from conserved variables per cell, in the order of the paper's
+// equation-of-state routine (Sec. "Python Code Generation and Immediate
+// Execution using NumPy"): rho = sum_k rho_k, Y_k = rho_k/rho, u = m/rho,
+// e = E/rho - |u|^2/2, T by the Newton inversion of e, p = rho R T/W.  The
+// partial densities are read twice (the second pass from cache): once to
+// form rho and the energy fold (over rho_k/W_k, then divided by rho), once to
+// write Y.
+template <int NG>
+__global__ __launch_bounds__(kBlock) void primitive_kernel(
+    DevMech m, int64_t n, int64_t ld, int dim, const double* __restrict__ rhok,
+    const double* __restrict__ mom, const double* __restrict__ E,
+    const double* __restrict__ Tg, double Tg_value, double* __restrict__ rho_out,
+    double* __restrict__ Y_out, double* __restrict__ u_out, double* __restrict__ T_out,
+    double* __restrict__ p_out, int32_t* __restrict__ status, int max_iter, double rtol) {
+    const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+    const bool valid = i < n;
+    const int64_t c = valid ? i : n - 1;
+    Mixture mx;
+    fold<NG>(m, rhok, ld, c, mx);   // coefficients weighted by rho_k/W_k
+    double rho = 0.0;
+    for (int k = 0; k < m.S; ++k) rho += rhok[size_t(k) * ld + c];
+    scale<NG>(mx, rho);             // now weighted by Y_k/W_k; xsum = 1/W
+    double kin = 0.0;
+    for (int d = 0; d < dim; ++d) {
+        const double u = mom[size_t(d) * ld + c] / rho;
+        kin = fma(u, u, kin);
+        if (valid) u_out[size_t(d) * ld + i] = u;
+    }
+    const double e = E[c] / rho - 0.5 * kin;
+    int32_t st;
+    const double T = newton_solve<NG, false>(m, mx, e * (1.0 / kGasConstant),
+                                             Tg ? Tg[c] : Tg_value, valid, max_iter, rtol, st);
+    if (!valid) return;
+    for (int k = 0; k < m.S; ++k) Y_out[size_t(k) * ld + i] = rhok[size_t(k) * ld + i] / rho;
+    rho_out[i] = rho;
+    T_out[i] = T;
+    p_out[i] = rho * kGasConstant * T * mx.xsum;
+    status[i] = st;
 }
 
 template <int NG>
@@ -134,24 +206,56 @@ unsigned grid(int64_t n) { return unsigned((n + kBlock - 1) / kBlock); }
 
 }  // namespace
 
+namespace {
+template <bool ENTHALPY>
+hipError_t launch_newton(const pyro_mech* m, int64_t n, int64_t ld, const double* e,
+                         const double* Y, const double* T_guess, double T_guess_value,
+                         double* T_out, int32_t* status, int max_iter, double rtol,
+                         hipStream_t stream) {
+    switch (m->dev.n_groups) {
+        case 1:
+            hipLaunchKernelGGL((newton_kernel<1, ENTHALPY>), dim3(grid(n)), dim3(kBlock), 0,
+                               stream, m->dev, n, ld, e, Y, T_guess, T_guess_value, T_out, status,
+                               max_iter, rtol);
+            break;
+        case 2:
+            hipLaunchKernelGGL((newton_kernel<2, ENTHALPY>), dim3(grid(n)), dim3(kBlock), 0,
+                               stream, m->dev, n, ld, e, Y, T_guess, T_guess_value, T_out, status,
+                               max_iter, rtol);
+            break;
+        default:
+            hipLaunchKernelGGL((newton_kernel<kMaxTmidGroups, ENTHALPY>), dim3(grid(n)),
+                               dim3(kBlock), 0, stream, m->dev, n, ld, e, Y, T_guess,
+                               T_guess_value, T_out, status, max_iter, rtol);
+    }
+    return hipGetLastError();
+}
+}  // namespace
+
 hipError_t launch_temperature(const pyro_mech* m, int64_t n, int64_t ld, const double* e,
                               const double* Y, const double* T_guess, double T_guess_value,
                               double* T_out, int32_t* status, int max_iter, double rtol,
-                              hipStream_t stream) {
-    switch (m->dev.n_groups) {
-        case 1:
-            hipLaunchKernelGGL(newton_kernel<1>, dim3(grid(n)), dim3(kBlock), 0, stream, m->dev, n,
-                               ld, e, Y, T_guess, T_guess_value, T_out, status, max_iter, rtol);
-            break;
-        case 2:
-            hipLaunchKernelGGL(newton_kernel<2>, dim3(grid(n)), dim3(kBlock), 0, stream, m->dev, n,
-                               ld, e, Y, T_guess, T_guess_value, T_out, status, max_iter, rtol);
-            break;
-        default:
-            hipLaunchKernelGGL(newton_kernel<kMaxTmidGroups>, dim3(grid(n)), dim3(kBlock), 0,
-                               stream, m->dev, n, ld, e, Y, T_guess, T_guess_value, T_out, status,
-                               max_iter, rtol);
-    }
+                              hipStream_t stream, bool enthalpy) {
+    if (enthalpy)
+        return launch_newton<true>(m, n, ld, e, Y, T_guess, T_guess_value, T_out, status,
+                                   max_iter, rtol, stream);
+    return launch_newton<false>(m, n, ld, e, Y, T_guess, T_guess_value, T_out, status, max_iter,
+                                rtol, stream);
+}
+
+hipError_t launch_primitive(const pyro_mech* m, int64_t n, int64_t ld, int dim,
+                            const double* rhok, const double* mom, const double* E,
+                            const double* T_guess, double T_guess_value, double* rho_out,
+                            double* Y_out, double* u_out, double* T_out, double* p_out,
+                            int32_t* status, int max_iter, double rtol, hipStream_t stream) {
+    if (m->dev.n_groups == 1)
+        hipLaunchKernelGGL(primitive_kernel<1>, dim3(grid(n)), dim3(kBlock), 0, stream, m->dev,
+                           n, ld, dim, rhok, mom, E, T_guess, T_guess_value, rho_out, Y_out, u_out,
+                           T_out, p_out, status, max_iter, rtol);
+    else
+        hipLaunchKernelGGL(primitive_kernel<kMaxTmidGroups>, dim3(grid(n)), dim3(kBlock), 0,
+                           stream, m->dev, n, ld, dim, rhok, mom, E, T_guess, T_guess_value,
+                           rho_out, Y_out, u_out, T_out, p_out, status, max_iter, rtol);
     return hipGetLastError();
 }
 

@@ -253,21 +253,35 @@ __device__ inline double wave_sum4(double a, double b, double c, double d, int l
 }
 
 // LDS of the reverse sweep: species rows, then a region holding the two
-// chunk buffers during the chunk loop and, after it, Mbar [n_pd][64] and the
-// per-wave temperature partials [kVjpWaves][64], then the parameter sums
+// chunk buffers during the chunk loop and, after it, Mbar [n_pd][64], the
+// per-wave temperature partials [kVjpWaves][64] and (Jacobian rows) the
+// per-wave heat-capacity partials [kVjpWaves][64], then the parameter sums
 __host__ __device__ inline size_t vjp_region_bytes(int n_pd) {
     const size_t chunks = 2 * 3 * size_t(kPlane);
-    const size_t after = (size_t(n_pd) + kVjpWaves) * kTile * 8;
+    const size_t after = (size_t(n_pd) + 2 * kVjpWaves) * kTile * 8;
     return chunks > after ? chunks : after;
 }
 
-// WITH_W: also the net production rates, gathered from a third plane (q)
-template <int MAXOWN, int MAXPD, bool WITH_W>
+// c_p/R of NASA7 a1..a5
+__device__ inline double cp_poly(const double* a, double T) {
+    return a[0] + T * (a[1] + T * (a[2] + T * (a[3] + T * a[4])));
+}
+
+// WITH_W: also the net production rates, gathered from a third plane (q).
+// JAC (0: the VJP; 1, 2: one row of the chemical Jacobian): the cotangent is
+// W_unit on species ``unit`` and zero elsewhere (not read from wbar), so Ybar
+// receives row ``unit`` of dS/dY with S_k = W_k omega_k at fixed T and Tbar
+// dS_unit/dT; reactions without species ``unit`` have a zero cotangent and
+// are skipped, and no parameter sums are formed.  JAC == 2 adds the
+// dependence of T on Y at fixed internal energy, dT/dY_k = -e_k/c_v.
+template <int MAXOWN, int MAXPD, bool WITH_W, int JAC = 0>
 __global__ __launch_bounds__(kVjpWaves * 64) void vjp_kernel(
     DevMech m, int64_t n, int64_t ld, const double* __restrict__ rho,
     const double* __restrict__ T, const double* __restrict__ Y,
     const double* __restrict__ wbar, double* __restrict__ Ybar, double* __restrict__ Tbar,
-    double* __restrict__ wdot, double* __restrict__ partial, const double* __restrict__ params) {
+    double* __restrict__ wdot, double* __restrict__ partial, const double* __restrict__ params,
+    int unit = -1) {
+    static_assert(JAC == 0 || !WITH_W, "Jacobian rows do not return omega");
     constexpr int kBuf = (WITH_W ? 3 : 2) * kPlane;   // one chunk buffer: a, b (, q) planes
     extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
     const DevSched& sc = m.vjp;
@@ -276,9 +290,15 @@ __global__ __launch_bounds__(kVjpWaves * 64) void vjp_kernel(
     unsigned char* bufs = lds + size_t(m.S) * kVRow;
     double* mbar = reinterpret_cast<double*>(bufs);                           // after the loop
     double* tb = mbar + size_t(m.n_pd) * kTile;                               // after the loop
+    double* cvb = tb + size_t(kVjpWaves) * kTile;                              // JAC: after the loop
     double* pacc = reinterpret_cast<double*>(bufs + vjp_region_bytes(m.n_pd)); // [R + n_fo][3]
     const int n_rows = m.R + m.n_fo;
-    for (int i = threadIdx.x; i < 3 * n_rows; i += kVjpWaves * 64) pacc[i] = 0.0;
+    if (JAC == 0)
+        for (int i = threadIdx.x; i < 3 * n_rows; i += kVjpWaves * 64) pacc[i] = 0.0;
+    // JAC: byte offset of the unit species' row (compared with the reaction
+    // records' participant offsets) and its molar mass
+    const int unit_off = unit * kVRow;
+    const double w_unit = JAC ? cst(m.w)[unit >= 0 ? unit : 0] : 0.0;
 
     const int nown = cst(sc.n_own)[w];
     const cptr<int32_t> own = cst(sc.own) + w * kMaxOwn;
@@ -298,13 +318,25 @@ __global__ __launch_bounds__(kVjpWaves * 64) void vjp_kernel(
 
         // ---- species phase: C, G and wbar (zero for cells past n, so those
         // lanes contribute nothing to any sum)
+        double cvp = 0.0;   // JAC == 2: this wave's part of c_v = sum_k Y_k c_v,k
 #pragma unroll
         for (int i = 0; i < MAXOWN; ++i) {
             if (i < nown) {
                 const int k = own[i];
                 const SpeciesRec s = cst(m.species)[k];
                 const double y = Y[size_t(k) * ld + c];
-                const double wb = valid ? wbar[size_t(k) * ld + c] : 0.0;
+                double wb;
+                if constexpr (JAC != 0) {
+                    wb = valid && k == unit ? w_unit : 0.0;
+                } else {
+                    wb = valid ? wbar[size_t(k) * ld + c] : 0.0;
+                }
+                if constexpr (JAC == 2) {
+                    // c_v,k = (c_p,k - R)/W_k, Y as given (eq. cv)
+                    const NewtonSpecies ns = cst(m.newton)[k];
+                    const double cpr = cs.T <= s.t_mid ? cp_poly(ns.lo, cs.T) : cp_poly(ns.hi, cs.T);
+                    cvp = fma(y * kGasConstant * s.inv_w, cpr - 1.0, cvp);
+                }
                 const double g_lo = gibbs_poly(s.lo, cs.T, omlnT, cs.invT);
                 const double g_hi = gibbs_poly(s.hi, cs.T, omlnT, cs.invT);
                 double* row = reinterpret_cast<double*>(lds + k * kVRow) + lane;
@@ -351,7 +383,25 @@ __global__ __launch_bounds__(kVjpWaves * 64) void vjp_kernel(
             unsigned char* plane_b = plane_a + kPlane;
             unsigned char* plane_q = plane_b + kPlane;
             const RxnRec r = cst(sc.rxn)[size_t(ch) * kVjpWaves + w];
-            if (r.cls != kNoReaction) {
+            // JAC: a reaction without the unit species has qbar = 0 and adds
+            // nothing; its slots are zeroed and its [M] slot consumed
+            bool skip = false;
+            if constexpr (JAC != 0) {
+                skip = true;
+                for (int i = 0; i < kMaxSide; ++i) {
+                    if (i < r.nr && r.r[i] == unit_off) skip = false;
+                    if (i < r.np && r.p[i] == unit_off) skip = false;
+                }
+                if (skip && r.cls != kNoReaction) {
+                    *reinterpret_cast<double*>(plane_a + r.qoff + lane * 8) = 0.0;
+                    *reinterpret_cast<double*>(plane_b + r.qoff + lane * 8) = 0.0;
+                    if (r.cls >= kThirdBody) {
+                        pop_front(Mr);
+                        Mr[MAXPD - 1] = 0.0;
+                    }
+                }
+            }
+            if (r.cls != kNoReaction && !skip) {
                 const double M = r.cls >= kThirdBody ? pop_front(Mr) : 1.0;
                 const RevOut o = reaction_vjp(m, r, params, lds, lane, M, cs);
                 *reinterpret_cast<double*>(plane_a + r.qoff + lane * 8) = o.a;
@@ -361,15 +411,17 @@ __global__ __launch_bounds__(kVjpWaves * 64) void vjp_kernel(
                 // the loop the queue's tail holds them in chunk order
                 if (r.cls >= kThirdBody) Mr[MAXPD - 1] = o.Mbar;
                 tbar += o.Tbar;
-                // cell sums of xbar (1, ln T, -1/(R T)) into this reaction's
-                // rows: lanes 0, 1, 2 hold the three totals
-                const double sx = wave_sum4(o.xbar, o.xbar * cs.lnT, -o.xbar * cs.invRT(), 0.0, lane);
-                double sf = 0.0;
-                if (r.cls >= kLindemann)
-                    sf = wave_sum4(o.xbar0, o.xbar0 * cs.lnT, -o.xbar0 * cs.invRT(), 0.0, lane);
-                if (lane < 3) {
-                    pacc[3 * r.prow + lane] += sx;
-                    if (r.cls >= kLindemann) pacc[3 * (m.R + r.fo) + lane] += sf;
+                if constexpr (JAC == 0) {
+                    // cell sums of xbar (1, ln T, -1/(R T)) into this reaction's
+                    // rows: lanes 0, 1, 2 hold the three totals
+                    const double sx = wave_sum4(o.xbar, o.xbar * cs.lnT, -o.xbar * cs.invRT(), 0.0, lane);
+                    double sf = 0.0;
+                    if (r.cls >= kLindemann)
+                        sf = wave_sum4(o.xbar0, o.xbar0 * cs.lnT, -o.xbar0 * cs.invRT(), 0.0, lane);
+                    if (lane < 3) {
+                        pacc[3 * r.prow + lane] += sx;
+                        if (r.cls >= kLindemann) pacc[3 * (m.R + r.fo) + lane] += sf;
+                    }
                 }
             }
             __syncthreads();
@@ -459,6 +511,7 @@ __global__ __launch_bounds__(kVjpWaves * 64) void vjp_kernel(
             }
         }
         // ---- species results
+        double ybs[JAC == 2 ? MAXOWN : 1], eks[JAC == 2 ? MAXOWN : 1];
 #pragma unroll
         for (int i = 0; i < MAXOWN; ++i) {
             if (i < nown) {
@@ -473,8 +526,13 @@ __global__ __launch_bounds__(kVjpWaves * 64) void vjp_kernel(
                 const NewtonSpecies ns = cst(m.newton)[k];
                 const double h_lo = enthalpy_poly(ns.lo, cs.T, cs.invT);
                 const double h_hi = enthalpy_poly(ns.hi, cs.T, cs.invT);
-                tbar -= gam[i] * (cs.T <= sp.t_mid ? h_lo : h_hi) * cs.invT;
-                if (valid) {
+                const double hRT = cs.T <= sp.t_mid ? h_lo : h_hi;
+                tbar -= gam[i] * hRT * cs.invT;
+                if constexpr (JAC == 2) {
+                    // held until dS/dT is known: e_k = (h_k - R T)/W_k (eq. int_energy)
+                    ybs[i] = ybar;
+                    eks[i] = kGasConstant * cs.T * (hRT - 1.0) * sp.inv_w;
+                } else if (valid) {
                     Ybar[size_t(k) * ld + cell] = ybar;
                     if (WITH_W) wdot[size_t(k) * ld + cell] = ws[i];
                 }
@@ -482,17 +540,33 @@ __global__ __launch_bounds__(kVjpWaves * 64) void vjp_kernel(
         }
         // ---- temperature: per-wave partials summed in wave order
         tb[w * kTile + lane] = tbar;
+        if (JAC == 2) cvb[w * kTile + lane] = cvp;
         __syncthreads();
-        if (w == 0) {
+        if constexpr (JAC == 2) {
+            // every wave forms the same sums in the same order, then applies
+            // dS/dY_k += dS/dT dT/dY_k with dT/dY_k = -e_k/c_v at fixed e
+            double st = 0.0, cv = 0.0;
+            for (int v = 0; v < kVjpWaves; ++v) {
+                st += tb[v * kTile + lane];
+                cv += cvb[v * kTile + lane];
+            }
+            const double g = st / cv;
+#pragma unroll
+            for (int i = 0; i < MAXOWN; ++i)
+                if (i < nown && valid) Ybar[size_t(own[i]) * ld + cell] = fma(-g, eks[i], ybs[i]);
+            if (w == 0 && valid && Tbar) Tbar[cell] = st;
+        } else if (w == 0) {
             double s = 0.0;
             for (int v = 0; v < kVjpWaves; ++v) s += tb[v * kTile + lane];
-            if (valid) Tbar[cell] = s;
+            if (valid && (JAC == 0 || Tbar)) Tbar[cell] = s;
         }
     }
-    // ---- this workgroup's parameter sums: [block][R + n_fo][3]
-    __syncthreads();
-    double* p = partial + size_t(blockIdx.x) * 3 * n_rows;
-    for (int i = threadIdx.x; i < 3 * n_rows; i += kVjpWaves * 64) p[i] = pacc[i];
+    if constexpr (JAC == 0) {
+        // ---- this workgroup's parameter sums: [block][R + n_fo][3]
+        __syncthreads();
+        double* p = partial + size_t(blockIdx.x) * 3 * n_rows;
+        for (int i = threadIdx.x; i < 3 * n_rows; i += kVjpWaves * 64) p[i] = pacc[i];
+    }
 }
 
 // pbar[row][f] = sum over workgroups of their sums, in workgroup order.
@@ -505,10 +579,11 @@ __global__ void vjp_reduce_kernel(int rows3, int blocks, const double* __restric
     pbar[idx] = s;
 }
 
-template <int MAXOWN, int MAXPD, bool WITH_W>
+template <int MAXOWN, int MAXPD, bool WITH_W, int JAC = 0>
 hipError_t set_lds_vjp(int bytes) {
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(&vjp_kernel<MAXOWN, MAXPD, WITH_W>),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    return hipFuncSetAttribute(
+        reinterpret_cast<const void*>(&vjp_kernel<MAXOWN, MAXPD, WITH_W, JAC>),
+        hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
 struct VjpArgs {
@@ -546,13 +621,67 @@ hipError_t set_lds_own(int bytes) {
     const hipError_t all[] = {
         set_lds_vjp<MAXOWN, 4, false>(bytes), set_lds_vjp<MAXOWN, 8, false>(bytes),
         set_lds_vjp<MAXOWN, 16, false>(bytes), set_lds_vjp<MAXOWN, 4, true>(bytes),
-        set_lds_vjp<MAXOWN, 8, true>(bytes), set_lds_vjp<MAXOWN, 16, true>(bytes)};
+        set_lds_vjp<MAXOWN, 8, true>(bytes), set_lds_vjp<MAXOWN, 16, true>(bytes),
+        set_lds_vjp<MAXOWN, 4, false, 1>(bytes), set_lds_vjp<MAXOWN, 8, false, 1>(bytes),
+        set_lds_vjp<MAXOWN, 16, false, 1>(bytes), set_lds_vjp<MAXOWN, 4, false, 2>(bytes),
+        set_lds_vjp<MAXOWN, 8, false, 2>(bytes), set_lds_vjp<MAXOWN, 16, false, 2>(bytes)};
     for (hipError_t x : all)
         if (x != hipSuccess) e = x;
     return e;
 }
 
+// One launch per Jacobian row: row j's cotangent is W_j on species j.
+template <int MAXOWN, int MAXPD, int JAC>
+hipError_t launch_jacobian_rows(const pyro_mech* m, int64_t n, int64_t ld, const double* rho,
+                                const double* T, const double* Y, double* J, double* dSdT,
+                                const double* params, hipStream_t stream) {
+    const int64_t n_tiles = (n + kTile - 1) / kTile;
+    const int blocks = int(std::min<int64_t>(n_tiles, int64_t(m->n_cu)));
+    const size_t lds = vjp_lds_bytes(m);
+    for (int j = 0; j < m->S; ++j) {
+        hipLaunchKernelGGL((vjp_kernel<MAXOWN, MAXPD, false, JAC>), dim3(unsigned(blocks)),
+                           dim3(kVjpWaves * 64), lds, stream, m->dev, n, ld, rho, T, Y,
+                           nullptr, J + size_t(j) * m->S * ld,
+                           dSdT ? dSdT + size_t(j) * ld : nullptr, nullptr, nullptr, params, j);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+template <int MAXOWN, int JAC>
+hipError_t launch_jacobian_own(const pyro_mech* m, int64_t n, int64_t ld, const double* rho,
+                               const double* T, const double* Y, double* J, double* dSdT,
+                               const double* params, hipStream_t stream) {
+    if (m->vjp_max_pdw <= 4)
+        return launch_jacobian_rows<MAXOWN, 4, JAC>(m, n, ld, rho, T, Y, J, dSdT, params, stream);
+    if (m->vjp_max_pdw <= 8)
+        return launch_jacobian_rows<MAXOWN, 8, JAC>(m, n, ld, rho, T, Y, J, dSdT, params, stream);
+    return launch_jacobian_rows<MAXOWN, 16, JAC>(m, n, ld, rho, T, Y, J, dSdT, params, stream);
+}
+
+template <int JAC>
+hipError_t launch_jacobian_mode(const pyro_mech* m, int64_t n, int64_t ld, const double* rho,
+                                const double* T, const double* Y, double* J, double* dSdT,
+                                const double* params, hipStream_t stream) {
+    if (m->vjp_max_own <= 4)
+        return launch_jacobian_own<4, JAC>(m, n, ld, rho, T, Y, J, dSdT, params, stream);
+    if (m->vjp_max_own <= 8)
+        return launch_jacobian_own<8, JAC>(m, n, ld, rho, T, Y, J, dSdT, params, stream);
+    return launch_jacobian_own<16, JAC>(m, n, ld, rho, T, Y, J, dSdT, params, stream);
+}
+
 }  // namespace
+
+hipError_t launch_chemical_jacobian(const pyro_mech* m, int64_t n, int64_t ld, const double* rho,
+                                    const double* T, const double* Y, int fixed_energy,
+                                    double* J, double* dSdT, const double* params,
+                                    hipStream_t stream) {
+    const double* p = params ? params : m->dev.params;
+    if (fixed_energy)
+        return launch_jacobian_mode<2>(m, n, ld, rho, T, Y, J, dSdT, p, stream);
+    return launch_jacobian_mode<1>(m, n, ld, rho, T, Y, J, dSdT, p, stream);
+}
 
 size_t vjp_lds_bytes(const pyro_mech* m) {
     return size_t(m->S) * kVRow + vjp_region_bytes(m->n_tb + m->n_fo) +

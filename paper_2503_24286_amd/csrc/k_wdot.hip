@@ -35,6 +35,16 @@
 // reversible reaction, and LDS holds C only (half the bytes per species),
 // which lets large mechanisms fit and raises occupancy.
 //
+// Log-space variant (LOG, with RKC): the species rows hold C_k and ln C_k,
+// and each rate is one exponential of a sum,
+//     R_f = exp(ln k + sum_r nu'_r ln C_r),
+//     R_r = exp(ln k + dg_j + dnu ln(R T/p0) + sum_p nu''_p ln C_p),
+// with ln [M] added for third-body reactions and ln(P_r/(1+P_r)) + ln F for
+// falloff ones: no intermediate (k, 1/K_c, products of C) can overflow or
+// underflow, so a rate is out of range only when the rate itself is.  The
+// kernel is templated on its arithmetic type; the FP32 production rates are
+// this variant in float (FP64 runs it too, as a selectable variant).
+//
 // MFMA third-body variant (MM): [M]_j = sum_k eps_jk C_k is a dense
 // contraction (every species has an efficiency), computed for the whole tile
 // as M[64 cells x n_pd] = C[64 x S] eps^T[S x n_pd] with v_mfma_f64_16x16x4f64
@@ -66,24 +76,33 @@ __device__ inline double recip(double x) {
     return r;
 }
 
-// g0/(R T) = c0 (1 - ln T) + c1 T + c2 T^2 + c3 T^3 + c4 T^4 + c5/T + c6.
-__device__ inline double gibbs_poly(const double* c, double T, double omlnT, double invT) {
-    return fma(c[0], omlnT, fma(c[5], invT, c[6])) +
-           T * fma(T, fma(T, fma(T, c[4], c[3]), c[2]), c[1]);
+// g0/(R T) = c0 (1 - ln T) + c1 T + c2 T^2 + c3 T^3 + c4 T^4 + c5/T + c6
+// (double coefficients, evaluated in the kernel's arithmetic type).
+template <typename real>
+__device__ inline real gibbs_poly(const double* c, real T, real omlnT, real invT) {
+    return fma(real(c[0]), omlnT, fma(real(c[5]), invT, real(c[6]))) +
+           T * fma(T, fma(T, fma(T, real(c[4]), real(c[3])), real(c[2])), real(c[1]));
 }
 
 // ln k of the Arrhenius triple in row ``row`` of ``params``.
-__device__ inline double log_arrhenius(const double* __restrict__ params, int row, double lnT,
-                                       double invRT) {
+template <typename real>
+__device__ inline real log_arrhenius(const double* __restrict__ params, int row, real lnT,
+                                     real invRT) {
     const double* p = params + 3 * row;
-    return fma(-p[2], invRT, fma(p[1], lnT, p[0]));
+    return fma(-real(p[2]), invRT, fma(real(p[1]), lnT, real(p[0])));
+}
+
+// ln(x/(1+x)) from u = ln x, for any u (both limits without overflow)
+template <typename real>
+__device__ inline real log_blend(real u) {
+    return u > real(0) ? -log1p(exp(-u)) : u - log1p(exp(u));
 }
 
 // Head of the wave's queue of third-body concentrations; the queue is
 // popped by shifting, so the values stay in registers with static indices.
-template <int N>
-__device__ inline double pop_front(double (&v)[N]) {
-    const double head = v[0];
+template <typename real, int N>
+__device__ inline real pop_front(real (&v)[N]) {
+    const real head = v[0];
 #pragma unroll
     for (int i = 0; i + 1 < N; ++i) v[i] = v[i + 1];
     return head;
@@ -93,6 +112,68 @@ __device__ inline double pop_front(double (&v)[N]) {
 // half as long as the C/G rows the offsets are given for)
 __device__ inline double lds_c(const unsigned char* lds, int off, int lane) {
     return reinterpret_cast<const double*>(lds + (off >> 1))[lane];
+}
+
+// ln C of the species at byte offset ``off`` (given for double C/G rows) of
+// a log-space row: C[64] then ln C[64] in the kernel's type
+template <typename real>
+__device__ inline real lds_lnc(const unsigned char* lds, int off, int lane) {
+    constexpr int sh = sizeof(real) == 4 ? 1 : 0;
+    return reinterpret_cast<const real*>(lds + (off >> sh))[kTile + lane];
+}
+
+// Log-space rate of progress (see the LOG variant above).
+template <typename real>
+__device__ inline real rate_of_progress_log(const DevMech& m, const RxnRec& r,
+                                            const double* __restrict__ params,
+                                            const unsigned char* lds, int lane, real lnk,
+                                            real M, real Tc, real lnT, real invT, real invRT,
+                                            real ln_rtp, cptr<double> kc) {
+    if (r.cls >= kLindemann) {
+        // ln P_r = ln k0 + ln [M] - ln k_inf; ln k += ln(P_r/(1+P_r)) + ln F
+        const real lpr = log_arrhenius<real>(params, m.R + r.fo, lnT, invRT) + log(M) - lnk;
+        real lnF = 0;
+        if (r.cls == kTroe) {
+            // ln F_cent of its three exponential terms without forming them
+            // (log-sum-exp), then both logarithms floored at log10 = -300 as
+            // F_cent and P_r are in the linear form
+            const FalloffRec f = m.falloff[r.fo];
+            const real t3 = log(real(1) - real(f.alpha)) + Tc * real(f.a3);
+            const real t1 = log(real(f.alpha)) + Tc * real(f.a1);
+            const real t2 = real(f.a2) * invT;
+            const real tm = fmax(t1, fmax(t2, t3));
+            const real lnfc = tm + log(exp(t1 - tm) + exp(t2 - tm) + exp(t3 - tm));
+            const real log10e = real(0.43429448190325182765);
+            const real lfc = fmax(lnfc * log10e, real(-300));
+            const real c = real(-0.4) - real(0.67) * lfc;
+            const real nn = real(0.75) - real(1.27) * lfc;
+            const real x = fmax(lpr * log10e, real(-300)) + c;
+            const real f1 = x / (nn - real(0.14) * x);
+            lnF = lfc / (real(1) + f1 * f1) * real(2.30258509299404568402);
+        }
+        lnk += log_blend(lpr) + lnF;
+    }
+    real xf = lnk + lds_lnc<real>(lds, r.r[0], lane);
+    if (r.nr > 1) {
+        xf += lds_lnc<real>(lds, r.r[1], lane);
+        if (r.nr > 2) xf += lds_lnc<real>(lds, r.r[2], lane);
+    }
+    const real lm = r.cls == kThirdBody ? log(M) : real(0);
+    real q = exp(xf + lm);
+    if (r.rev) {
+        real xr = lnk + real(r.dnu) * ln_rtp + lds_lnc<real>(lds, r.p[0], lane);
+        if (r.np > 1) {
+            xr += lds_lnc<real>(lds, r.p[1], lane);
+            if (r.np > 2) xr += lds_lnc<real>(lds, r.p[2], lane);
+        }
+        const double lo[7] = {kc[0], kc[1], kc[2], kc[3], kc[4], kc[5], kc[6]};
+        const double hi[7] = {kc[7], kc[8], kc[9], kc[10], kc[11], kc[12], kc[13]};
+        const real omlnT = real(1) - lnT;
+        const real d_lo = gibbs_poly<real>(lo, Tc, omlnT, invT);
+        const real d_hi = gibbs_poly<real>(hi, Tc, omlnT, invT);
+        q -= exp(xr + (Tc <= real(kc[14]) ? d_lo : d_hi) + lm);
+    }
+    return q;
 }
 
 // Rate of progress of one reaction for the calling lane's cell, given its
@@ -107,7 +188,7 @@ __device__ inline double rate_of_progress(const DevMech& m, const RxnRec& r,
                                           double invRT, double rtp, double irtp,
                                           cptr<double> kc) {
     if (r.cls >= kLindemann) {
-        const double k0 = exp(log_arrhenius(params, m.R + r.fo, lnT, invRT));
+        const double k0 = exp(log_arrhenius<double>(params, m.R + r.fo, lnT, invRT));
         const double Pr = k0 * M / kf;
         double F = 1.0;
         if (r.cls == kTroe) {
@@ -145,8 +226,8 @@ __device__ inline double rate_of_progress(const DevMech& m, const RxnRec& r,
             const double lo[7] = {kc[0], kc[1], kc[2], kc[3], kc[4], kc[5], kc[6]};
             const double hi[7] = {kc[7], kc[8], kc[9], kc[10], kc[11], kc[12], kc[13]};
             const double omlnT = 1.0 - lnT;
-            const double d_lo = gibbs_poly(lo, Tc, omlnT, invT);
-            const double d_hi = gibbs_poly(hi, Tc, omlnT, invT);
+            const double d_lo = gibbs_poly<double>(lo, Tc, omlnT, invT);
+            const double d_hi = gibbs_poly<double>(hi, Tc, omlnT, invT);
             q -= kf * pw * exp(Tc <= kc[14] ? d_lo : d_hi) * cp;
         }
         if (r.cls == kThirdBody) q *= M;
@@ -190,12 +271,17 @@ __device__ inline double rate_of_progress(const DevMech& m, const RxnRec& r,
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-template <int WAVES, int MAXOWN, int MAXPD, bool RKC, bool MM, bool NQ>
-__global__ __launch_bounds__(WAVES * 64) void wdot_f64_kernel(
-    DevMech m, int64_t n, int64_t ld, const double* __restrict__ rho,
-    const double* __restrict__ T, const double* __restrict__ Y,
-    double* __restrict__ wdot, const double* __restrict__ params,
+// real: the arithmetic and cell-array type (double, or float with LOG).
+template <typename real, int WAVES, int MAXOWN, int MAXPD, bool RKC, bool MM, bool NQ, bool LOG>
+__global__ __launch_bounds__(WAVES * 64) void wdot_kernel(
+    DevMech m, int64_t n, int64_t ld, const real* __restrict__ rho,
+    const real* __restrict__ T, const real* __restrict__ Y,
+    real* __restrict__ wdot, const double* __restrict__ params,
     const int64_t* __restrict__ n_dev) {
+    static_assert(!LOG || RKC, "the log-space form uses the combined Gibbs coefficients");
+    static_assert(sizeof(real) == 8 || (LOG && !MM && !NQ), "float runs the log-space form only");
+    // byte offsets in the tables are given for double rows and slots
+    constexpr int sh = sizeof(real) == 4 ? 1 : 0;
     extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
     if (n_dev) {
         n = *n_dev;  // cells counted on the device (the whole workgroup agrees)
@@ -207,48 +293,50 @@ __global__ __launch_bounds__(WAVES * 64) void wdot_f64_kernel(
     const bool valid = cell < n;
     const int64_t c = valid ? cell : n - 1;
 
-    const double Tc = T[c];
-    const double rc = rho[c];
-    const double lnT = log(Tc);
-    const double invT = 1.0 / Tc;
-    const double invRT = invT * (1.0 / kGasConstant);
-    const double rtp = kGasConstant * Tc / kOneAtm;
-    const double irtp = 1.0 / rtp;
-    const double omlnT = 1.0 - lnT;
+    const real Tc = T[c];
+    const real rc = rho[c];
+    const real lnT = log(Tc);
+    const real invT = real(1) / Tc;
+    const real invRT = invT * real(1.0 / kGasConstant);
+    const real rtp = real(kGasConstant / kOneAtm) * Tc;
+    const real irtp = real(1) / rtp;
+    const real ln_rtp = LOG ? log(rtp) : real(0);
+    const real omlnT = real(1) - lnT;
 
     // ---- species phase: all of this wave's mass-fraction loads first
     const int nown = m.n_own[w];
     const int32_t* own = m.own + w * kMaxOwn;
-    double y[MAXOWN];
+    real y[MAXOWN];
 #pragma unroll
     for (int i = 0; i < MAXOWN; ++i)
         if (i < nown) y[i] = Y[size_t(own[i]) * ld + c];
+    // row bytes: C and G (species variant), C (reaction variant), C and ln C (log)
+    constexpr int rowb = (LOG ? kRow : RKC ? kRowC : kRow) >> sh;
 #pragma unroll
     for (int i = 0; i < MAXOWN; ++i) {
         if (i < nown) {
             const int k = own[i];
             const SpeciesRec& s = m.species[k];
-            const double Ck = rc * fmax(y[i], 0.0) * s.inv_w;
-            if constexpr (RKC) {
-                reinterpret_cast<double*>(lds + k * kRowC)[lane] = Ck;
-            } else {
+            const real Ck = rc * fmax(y[i], real(0)) * real(s.inv_w);
+            real* row = reinterpret_cast<real*>(lds + k * rowb) + lane;
+            row[0] = Ck;
+            if constexpr (LOG) {
+                row[kTile] = log(Ck);
+            } else if constexpr (!RKC) {
                 // both ranges from scalar loads, then a per-lane select of the
                 // value (selecting the coefficient address would turn the
                 // uniform table reads into per-lane vector loads)
-                const double g_lo = gibbs_poly(s.lo, Tc, omlnT, invT);
-                const double g_hi = gibbs_poly(s.hi, Tc, omlnT, invT);
-                const double gRT = Tc <= s.t_mid ? g_lo : g_hi;
-                double* row = reinterpret_cast<double*>(lds + k * kRow) + lane;
-                row[0] = Ck;
+                const real g_lo = gibbs_poly<real>(s.lo, Tc, omlnT, invT);
+                const real g_hi = gibbs_poly<real>(s.hi, Tc, omlnT, invT);
+                const real gRT = Tc <= real(s.t_mid) ? g_lo : g_hi;
                 row[kTile] = exp(gRT);
             }
         }
     }
     __syncthreads();
 
-    constexpr int rowb = RKC ? kRowC : kRow;
     unsigned char* qbase = lds + size_t(m.S) * rowb;
-    constexpr int qbuf = WAVES * kRxnPerWave * kTile * 8;     // bytes per chunk buffer
+    constexpr int qbuf = WAVES * kRxnPerWave * kTile * sizeof(real);   // bytes per chunk buffer
     static_assert(!NQ || WAVES == kWaves, "the MFMA net rates assume kWaves wavefronts");
     double* Ml = reinterpret_cast<double*>(qbase + 2 * qbuf);  // MM: [n_pd16][64]
     if constexpr (MM) {
@@ -274,22 +362,22 @@ __global__ __launch_bounds__(WAVES * 64) void wdot_f64_kernel(
     }
 
     // ---- third-body concentrations of this wave's reactions
-    double Mr[MAXPD];
+    real Mr[MAXPD];
 #pragma unroll
-    for (int i = 0; i < MAXPD; ++i) Mr[i] = 0.0;
+    for (int i = 0; i < MAXPD; ++i) Mr[i] = real(0);
     if (!MM && m.n_pdw[w] > 0) {
         const double* ew = m.effw + size_t(w) * m.S * MAXPD;
         for (int k = 0; k < m.S; ++k) {
-            const double ck = reinterpret_cast<const double*>(lds + k * rowb)[lane];
+            const real ck = reinterpret_cast<const real*>(lds + k * rowb)[lane];
 #pragma unroll
-            for (int i = 0; i < MAXPD; ++i) Mr[i] = fma(ew[k * MAXPD + i], ck, Mr[i]);
+            for (int i = 0; i < MAXPD; ++i) Mr[i] = fma(real(ew[k * MAXPD + i]), ck, Mr[i]);
         }
     }
 
     // ---- reaction chunks and gathering
-    double acc[NQ ? 1 : MAXOWN];
+    real acc[NQ ? 1 : MAXOWN];
 #pragma unroll
-    for (int i = 0; i < (NQ ? 1 : MAXOWN); ++i) acc[i] = 0.0;
+    for (int i = 0; i < (NQ ? 1 : MAXOWN); ++i) acc[i] = real(0);
     // NQ: omega[64 cells x S] accumulated on the matrix cores over the chunks,
     // omega += q[cells x 16 slots] nu[16 slots x S]; wave w holds the
     // 16-cell x 16-species output blocks (cell block w & 3, species blocks
@@ -311,29 +399,45 @@ __global__ __launch_bounds__(WAVES * 64) void wdot_f64_kernel(
         const RxnRec* rb = m.rxn + (size_t(ch) * WAVES + w) * kRxnPerWave;
         const RxnRec r0 = rb[0];
         const RxnRec r1 = rb[1];
-        // both Arrhenius exponentials in one block, so they interleave
-        const double kf0 = exp(log_arrhenius(params, r0.prow, lnT, invRT));
-        const double kf1 = exp(log_arrhenius(params, r1.prow, lnT, invRT));
         // the wave meets its third-body/falloff reactions in queue order
-        double M0 = 1.0, M1 = 1.0;
+        real M0 = real(1), M1 = real(1);
         if constexpr (MM) {
             if (r0.cls >= kThirdBody) M0 = Ml[r0.pd * kTile + lane];
             if (r1.cls >= kThirdBody) M1 = Ml[r1.pd * kTile + lane];
         } else {
-            M0 = r0.cls >= kThirdBody ? pop_front(Mr) : 1.0;
-            M1 = r1.cls >= kThirdBody ? pop_front(Mr) : 1.0;
+            M0 = r0.cls >= kThirdBody ? pop_front(Mr) : real(1);
+            M1 = r1.cls >= kThirdBody ? pop_front(Mr) : real(1);
         }
         const cptr<double> kc = cst(m.rxn_kc) + (size_t(ch) * WAVES + w) * kRxnPerWave * 16;
+        real q0 = real(0), q1 = real(0);
+        if constexpr (LOG) {
+            const real lk0 = log_arrhenius<real>(params, r0.prow, lnT, invRT);
+            const real lk1 = log_arrhenius<real>(params, r1.prow, lnT, invRT);
+            if (r0.cls != kNoReaction)
+                q0 = rate_of_progress_log<real>(m, r0, params, lds, lane, lk0, M0, Tc, lnT, invT,
+                                                invRT, ln_rtp, kc);
+            if (r1.cls != kNoReaction)
+                q1 = rate_of_progress_log<real>(m, r1, params, lds, lane, lk1, M1, Tc, lnT, invT,
+                                                invRT, ln_rtp, kc + 16);
+        } else {
+            // both Arrhenius exponentials in one block, so they interleave
+            const double kf0 = exp(log_arrhenius<double>(params, r0.prow, lnT, invRT));
+            const double kf1 = exp(log_arrhenius<double>(params, r1.prow, lnT, invRT));
+            if (r0.cls != kNoReaction)
+                q0 = rate_of_progress<RKC>(m, r0, params, lds, lane, kf0, M0, Tc, lnT, invT,
+                                           invRT, rtp, irtp, kc);
+            if (r1.cls != kNoReaction)
+                q1 = rate_of_progress<RKC>(m, r1, params, lds, lane, kf1, M1, Tc, lnT, invT,
+                                           invRT, rtp, irtp, kc + 16);
+        }
         if (r0.cls != kNoReaction)
-            *reinterpret_cast<double*>(qb + r0.qoff + lane * 8) = rate_of_progress<RKC>(
-                m, r0, params, lds, lane, kf0, M0, Tc, lnT, invT, invRT, rtp, irtp, kc);
+            *reinterpret_cast<real*>(qb + (r0.qoff >> sh) + lane * sizeof(real)) = q0;
         else if (NQ)   // empty slots enter the dense product: zero, not stale LDS
-            *reinterpret_cast<double*>(qb + (2 * w) * kTile * 8 + lane * 8) = 0.0;
+            *reinterpret_cast<real*>(qb + (2 * w) * kTile * sizeof(real) + lane * sizeof(real)) = real(0);
         if (r1.cls != kNoReaction)
-            *reinterpret_cast<double*>(qb + r1.qoff + lane * 8) = rate_of_progress<RKC>(
-                m, r1, params, lds, lane, kf1, M1, Tc, lnT, invT, invRT, rtp, irtp, kc + 16);
+            *reinterpret_cast<real*>(qb + (r1.qoff >> sh) + lane * sizeof(real)) = q1;
         else if (NQ)
-            *reinterpret_cast<double*>(qb + (2 * w + 1) * kTile * 8 + lane * 8) = 0.0;
+            *reinterpret_cast<real*>(qb + (2 * w + 1) * kTile * sizeof(real) + lane * sizeof(real)) = real(0);
         __syncthreads();
         if constexpr (NQ) {
             // A[cell][slot]: slot 4 kk + l/16, cell 16 cb + l%16 of the chunk buffer
@@ -353,24 +457,25 @@ __global__ __launch_bounds__(WAVES * 64) void wdot_f64_kernel(
         int32_t bound[MAXOWN + 1];
 #pragma unroll
         for (int i = 0; i <= MAXOWN; ++i) bound[i] = gp[i];
+        const unsigned char* ql = qb + lane * sizeof(real);
 #pragma unroll
         for (int i = 0; i < MAXOWN; ++i) {
             if (i < nown) {
-                double a = acc[i], b = 0.0;
+                real a = acc[i], b = real(0);
                 int e = bound[i];
                 const int e1 = bound[i + 1];
                 for (; e + 1 < e1; e += 2) {
                     const GatherEntry g0 = m.gent[e];
                     const GatherEntry g1 = m.gent[e + 1];
-                    const double q0 = *reinterpret_cast<const double*>(qb + (g0 & 0xffffu) + lane * 8);
-                    const double q1 = *reinterpret_cast<const double*>(qb + (g1 & 0xffffu) + lane * 8);
-                    a = fma(double(int16_t(g0 >> 16)), q0, a);
-                    b = fma(double(int16_t(g1 >> 16)), q1, b);
+                    const real v0 = *reinterpret_cast<const real*>(ql + ((g0 & 0xffffu) >> sh));
+                    const real v1 = *reinterpret_cast<const real*>(ql + ((g1 & 0xffffu) >> sh));
+                    a = fma(real(int16_t(g0 >> 16)), v0, a);
+                    b = fma(real(int16_t(g1 >> 16)), v1, b);
                 }
                 if (e < e1) {
                     const GatherEntry g0 = m.gent[e];
-                    a = fma(double(int16_t(g0 >> 16)),
-                            *reinterpret_cast<const double*>(qb + (g0 & 0xffffu) + lane * 8), a);
+                    a = fma(real(int16_t(g0 >> 16)),
+                            *reinterpret_cast<const real*>(ql + ((g0 & 0xffffu) >> sh)), a);
                 }
                 acc[i] = a + b;
             }
@@ -396,57 +501,57 @@ __global__ __launch_bounds__(WAVES * 64) void wdot_f64_kernel(
     }
 }
 
-template <int WAVES, int MAXOWN, int MAXPD, bool RKC, bool MM, bool NQ>
-hipError_t launch_f64(const pyro_mech* m, int64_t n, int64_t ld, const double* rho,
-                      const double* T, const double* Y, double* wdot,
-                      const double* params, hipStream_t stream, const int64_t* n_dev) {
-    const size_t lds = production_rates_lds_bytes(m, RKC, MM);
+template <typename real, int WAVES, int MAXOWN, int MAXPD, bool RKC, bool MM, bool NQ, bool LOG>
+hipError_t launch_k(const pyro_mech* m, int64_t n, int64_t ld, const real* rho, const real* T,
+                    const real* Y, real* wdot, const double* params, hipStream_t stream,
+                    const int64_t* n_dev) {
+    const size_t lds = production_rates_lds_bytes(m, RKC, MM, LOG, sizeof(real));
     const int64_t blocks = (n + kTile - 1) / kTile;
-    hipLaunchKernelGGL((wdot_f64_kernel<WAVES, MAXOWN, MAXPD, RKC, MM, NQ>), dim3(unsigned(blocks)),
-                       dim3(WAVES * 64), lds, stream, m->dev, n, ld, rho, T, Y, wdot,
-                       params ? params : m->dev.params, n_dev);
+    hipLaunchKernelGGL((wdot_kernel<real, WAVES, MAXOWN, MAXPD, RKC, MM, NQ, LOG>),
+                       dim3(unsigned(blocks)), dim3(WAVES * 64), lds, stream, m->dev, n, ld, rho,
+                       T, Y, wdot, params ? params : m->dev.params, n_dev);
     return hipGetLastError();
 }
 
-// Kernel instances: (wavefronts, species owned per wave, [M] slots per wave,
-// variant).  With 2 kWaves wavefronts (large mechanisms, reaction variant
-// only) a wave owns at most 16 species.
-template <int WAVES, int MAXOWN, int MAXPD, bool RKC, bool MM, bool NQ>
+// Kernel instances: (type, wavefronts, species owned per wave, [M] slots per
+// wave, variant).  With 2 kWaves wavefronts (large mechanisms, reaction
+// variant only) a wave owns at most 16 species.
+template <typename real, int WAVES, int MAXOWN, int MAXPD, bool RKC, bool MM, bool NQ, bool LOG>
 hipError_t set_lds(int bytes) {
     return hipFuncSetAttribute(
-        reinterpret_cast<const void*>(&wdot_f64_kernel<WAVES, MAXOWN, MAXPD, RKC, MM, NQ>),
+        reinterpret_cast<const void*>(&wdot_kernel<real, WAVES, MAXOWN, MAXPD, RKC, MM, NQ, LOG>),
         hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
 // the NQ instances exist for at most 16 species per wave (NQ needs S <= 64)
-template <int MAXPD, bool RKC, bool MM, bool NQ>
-hipError_t dispatch_own(const pyro_mech* m, int64_t n, int64_t ld, const double* r,
-                        const double* t, const double* y, double* o, const double* params,
-                        hipStream_t stream, const int64_t* nd) {
+template <typename real, int MAXPD, bool RKC, bool MM, bool NQ, bool LOG>
+hipError_t dispatch_own(const pyro_mech* m, int64_t n, int64_t ld, const real* r, const real* t,
+                        const real* y, real* o, const double* params, hipStream_t stream,
+                        const int64_t* nd) {
     if constexpr (RKC && !NQ) {
         if (m->fw_waves != kWaves) {
             if (m->max_own <= 8)
-                return launch_f64<2 * kWaves, 8, MAXPD, RKC, MM, false>(m, n, ld, r, t, y, o, params, stream, nd);
-            return launch_f64<2 * kWaves, 16, MAXPD, RKC, MM, false>(m, n, ld, r, t, y, o, params, stream, nd);
+                return launch_k<real, 2 * kWaves, 8, MAXPD, RKC, MM, false, LOG>(m, n, ld, r, t, y, o, params, stream, nd);
+            return launch_k<real, 2 * kWaves, 16, MAXPD, RKC, MM, false, LOG>(m, n, ld, r, t, y, o, params, stream, nd);
         }
     }
-    if (m->max_own <= 8) return launch_f64<kWaves, 8, MAXPD, RKC, MM, NQ>(m, n, ld, r, t, y, o, params, stream, nd);
+    if (m->max_own <= 8) return launch_k<real, kWaves, 8, MAXPD, RKC, MM, NQ, LOG>(m, n, ld, r, t, y, o, params, stream, nd);
     if (NQ || m->max_own <= 16)
-        return launch_f64<kWaves, 16, MAXPD, RKC, MM, NQ>(m, n, ld, r, t, y, o, params, stream, nd);
-    if (m->max_own <= 32) return launch_f64<kWaves, 32, MAXPD, RKC, MM, false>(m, n, ld, r, t, y, o, params, stream, nd);
-    return launch_f64<kWaves, 64, MAXPD, RKC, MM, false>(m, n, ld, r, t, y, o, params, stream, nd);
+        return launch_k<real, kWaves, 16, MAXPD, RKC, MM, NQ, LOG>(m, n, ld, r, t, y, o, params, stream, nd);
+    if (m->max_own <= 32) return launch_k<real, kWaves, 32, MAXPD, RKC, MM, false, LOG>(m, n, ld, r, t, y, o, params, stream, nd);
+    return launch_k<real, kWaves, 64, MAXPD, RKC, MM, false, LOG>(m, n, ld, r, t, y, o, params, stream, nd);
 }
 
-template <bool RKC, bool MM, bool NQ>
+template <typename real, bool RKC, bool MM, bool NQ, bool LOG>
 hipError_t set_lds_variant(const pyro_mech* m, int bytes) {
     hipError_t e = hipSuccess;
     if constexpr (RKC && !NQ) {
         if (m->fw_waves != kWaves) {
             const hipError_t big[] = {
-                set_lds<2 * kWaves, 8, 8, RKC, MM, false>(bytes),
-                set_lds<2 * kWaves, 16, 8, RKC, MM, false>(bytes),
-                MM ? hipSuccess : set_lds<2 * kWaves, 8, 16, RKC, MM, false>(bytes),
-                MM ? hipSuccess : set_lds<2 * kWaves, 16, 16, RKC, MM, false>(bytes)};
+                set_lds<real, 2 * kWaves, 8, 8, RKC, MM, false, LOG>(bytes),
+                set_lds<real, 2 * kWaves, 16, 8, RKC, MM, false, LOG>(bytes),
+                MM ? hipSuccess : set_lds<real, 2 * kWaves, 8, 16, RKC, MM, false, LOG>(bytes),
+                MM ? hipSuccess : set_lds<real, 2 * kWaves, 16, 16, RKC, MM, false, LOG>(bytes)};
             for (hipError_t x : big)
                 if (x != hipSuccess) e = x;
             return e;
@@ -454,33 +559,45 @@ hipError_t set_lds_variant(const pyro_mech* m, int bytes) {
     }
     // the MFMA third-body variant holds no per-wave [M] slots: one MAXPD instance
     const hipError_t all[] = {
-        set_lds<kWaves, 8, 8, RKC, MM, NQ>(bytes),  set_lds<kWaves, 16, 8, RKC, MM, NQ>(bytes),
-        NQ ? hipSuccess : set_lds<kWaves, 32, 8, RKC, MM, false>(bytes),
-        NQ ? hipSuccess : set_lds<kWaves, 64, 8, RKC, MM, false>(bytes),
-        MM ? hipSuccess : set_lds<kWaves, 8, 16, RKC, MM, NQ>(bytes),
-        MM ? hipSuccess : set_lds<kWaves, 16, 16, RKC, MM, NQ>(bytes),
-        MM || NQ ? hipSuccess : set_lds<kWaves, 32, 16, RKC, MM, false>(bytes),
-        MM || NQ ? hipSuccess : set_lds<kWaves, 64, 16, RKC, MM, false>(bytes)};
+        set_lds<real, kWaves, 8, 8, RKC, MM, NQ, LOG>(bytes),
+        set_lds<real, kWaves, 16, 8, RKC, MM, NQ, LOG>(bytes),
+        NQ ? hipSuccess : set_lds<real, kWaves, 32, 8, RKC, MM, false, LOG>(bytes),
+        NQ ? hipSuccess : set_lds<real, kWaves, 64, 8, RKC, MM, false, LOG>(bytes),
+        MM ? hipSuccess : set_lds<real, kWaves, 8, 16, RKC, MM, NQ, LOG>(bytes),
+        MM ? hipSuccess : set_lds<real, kWaves, 16, 16, RKC, MM, NQ, LOG>(bytes),
+        MM || NQ ? hipSuccess : set_lds<real, kWaves, 32, 16, RKC, MM, false, LOG>(bytes),
+        MM || NQ ? hipSuccess : set_lds<real, kWaves, 64, 16, RKC, MM, false, LOG>(bytes)};
     for (hipError_t x : all)
         if (x != hipSuccess) e = x;
     return e;
 }
 
-template <bool RKC, bool MM, bool NQ>
-hipError_t dispatch_variant(const pyro_mech* m, int64_t n, int64_t ld, const double* r,
-                            const double* t, const double* y, double* o, const double* params,
+template <typename real, bool RKC, bool MM, bool NQ, bool LOG>
+hipError_t dispatch_variant(const pyro_mech* m, int64_t n, int64_t ld, const void* r,
+                            const void* t, const void* y, void* o, const double* params,
                             hipStream_t stream, const int64_t* nd) {
-    if (MM || m->max_pdw <= 8) return dispatch_own<8, RKC, MM, NQ>(m, n, ld, r, t, y, o, params, stream, nd);
-    return dispatch_own<16, RKC, MM, NQ>(m, n, ld, r, t, y, o, params, stream, nd);
+    const real* rr = static_cast<const real*>(r);
+    const real* tt = static_cast<const real*>(t);
+    const real* yy = static_cast<const real*>(y);
+    real* oo = static_cast<real*>(o);
+    if (MM || m->max_pdw <= 8)
+        return dispatch_own<real, 8, RKC, MM, NQ, LOG>(m, n, ld, rr, tt, yy, oo, params, stream, nd);
+    return dispatch_own<real, 16, RKC, MM, NQ, LOG>(m, n, ld, rr, tt, yy, oo, params, stream, nd);
 }
 
 }  // namespace
 
 size_t production_rates_lds_bytes(const pyro_mech* m, bool reaction_equilibrium,
-                                  bool mfma_third_body) {
-    return size_t(m->S) * (reaction_equilibrium ? kRowC : kRow) +
-           2 * size_t(m->fw_waves) * kRxnPerWave * kTile * 8 +
+                                  bool mfma_third_body, bool log_space, int real_bytes) {
+    // species rows: C and G (species variant), C (reaction variant) or C and
+    // ln C (log-space), 64 values each; two chunk buffers of rates; [M] block
+    const size_t row = size_t(kTile) * real_bytes * (log_space || !reaction_equilibrium ? 2 : 1);
+    return size_t(m->S) * row + 2 * size_t(m->fw_waves) * kRxnPerWave * kTile * real_bytes +
            (mfma_third_body ? size_t((m->n_tb + m->n_fo + 15) / 16 * 16) * kTile * 8 : 0);
+}
+
+bool log_space_supported(const pyro_mech* m, int real_bytes) {
+    return m->kc_ok && production_rates_lds_bytes(m, true, false, true, real_bytes) <= 160 * 1024;
 }
 
 hipError_t prepare_production_rates(const pyro_mech* m) {
@@ -491,15 +608,25 @@ hipError_t prepare_production_rates(const pyro_mech* m) {
         if (bytes > 160 * 1024 || (rkc && !m->kc_ok) || (nq && !nq_supported(m))) continue;
         hipError_t x;
         switch (v) {
-            case 0: x = set_lds_variant<false, false, false>(m, int(bytes)); break;
-            case 1: x = set_lds_variant<true, false, false>(m, int(bytes)); break;
-            case 2: x = set_lds_variant<false, true, false>(m, int(bytes)); break;
-            case 3: x = set_lds_variant<true, true, false>(m, int(bytes)); break;
-            case 4: x = set_lds_variant<false, false, true>(m, int(bytes)); break;
-            case 5: x = set_lds_variant<true, false, true>(m, int(bytes)); break;
-            case 6: x = set_lds_variant<false, true, true>(m, int(bytes)); break;
-            default: x = set_lds_variant<true, true, true>(m, int(bytes));
+            case 0: x = set_lds_variant<double, false, false, false, false>(m, int(bytes)); break;
+            case 1: x = set_lds_variant<double, true, false, false, false>(m, int(bytes)); break;
+            case 2: x = set_lds_variant<double, false, true, false, false>(m, int(bytes)); break;
+            case 3: x = set_lds_variant<double, true, true, false, false>(m, int(bytes)); break;
+            case 4: x = set_lds_variant<double, false, false, true, false>(m, int(bytes)); break;
+            case 5: x = set_lds_variant<double, true, false, true, false>(m, int(bytes)); break;
+            case 6: x = set_lds_variant<double, false, true, true, false>(m, int(bytes)); break;
+            default: x = set_lds_variant<double, true, true, true, false>(m, int(bytes));
         }
+        if (x != hipSuccess) e = x;
+    }
+    if (log_space_supported(m, 8)) {
+        const hipError_t x = set_lds_variant<double, true, false, false, true>(
+            m, int(production_rates_lds_bytes(m, true, false, true, 8)));
+        if (x != hipSuccess) e = x;
+    }
+    if (log_space_supported(m, 4)) {
+        const hipError_t x = set_lds_variant<float, true, false, false, true>(
+            m, int(production_rates_lds_bytes(m, true, false, true, 4)));
         if (x != hipSuccess) e = x;
     }
     return e;
@@ -510,23 +637,22 @@ bool nq_supported(const pyro_mech* m) {
 }
 
 hipError_t launch_production_rates(const pyro_mech* m, int64_t n, int64_t ld, int dtype,
-                                   const void* rho, const void* T, const void* Y,
-                                   void* wdot, const double* params, hipStream_t stream,
-                                   const int64_t* n_dev) {
-    (void)dtype;
-    const double* r = static_cast<const double*>(rho);
-    const double* t = static_cast<const double*>(T);
-    const double* y = static_cast<const double*>(Y);
-    double* o = static_cast<double*>(wdot);
+                                   const void* r, const void* t, const void* y, void* o,
+                                   const double* params, hipStream_t stream,
+                                   const int64_t* nd) {
+    // FP32: the log-space form in float (the only float instance)
+    if (dtype == PYRO_F32)
+        return dispatch_variant<float, true, false, false, true>(m, n, ld, r, t, y, o, params, stream, nd);
     switch (m->wdot_variant) {
-        case 1: return dispatch_variant<true, false, false>(m, n, ld, r, t, y, o, params, stream, n_dev);
-        case 2: return dispatch_variant<false, true, false>(m, n, ld, r, t, y, o, params, stream, n_dev);
-        case 3: return dispatch_variant<true, true, false>(m, n, ld, r, t, y, o, params, stream, n_dev);
-        case 4: return dispatch_variant<false, false, true>(m, n, ld, r, t, y, o, params, stream, n_dev);
-        case 5: return dispatch_variant<true, false, true>(m, n, ld, r, t, y, o, params, stream, n_dev);
-        case 6: return dispatch_variant<false, true, true>(m, n, ld, r, t, y, o, params, stream, n_dev);
-        case 7: return dispatch_variant<true, true, true>(m, n, ld, r, t, y, o, params, stream, n_dev);
-        default: return dispatch_variant<false, false, false>(m, n, ld, r, t, y, o, params, stream, n_dev);
+        case 1: return dispatch_variant<double, true, false, false, false>(m, n, ld, r, t, y, o, params, stream, nd);
+        case 2: return dispatch_variant<double, false, true, false, false>(m, n, ld, r, t, y, o, params, stream, nd);
+        case 3: return dispatch_variant<double, true, true, false, false>(m, n, ld, r, t, y, o, params, stream, nd);
+        case 4: return dispatch_variant<double, false, false, true, false>(m, n, ld, r, t, y, o, params, stream, nd);
+        case 5: return dispatch_variant<double, true, false, true, false>(m, n, ld, r, t, y, o, params, stream, nd);
+        case 6: return dispatch_variant<double, false, true, true, false>(m, n, ld, r, t, y, o, params, stream, nd);
+        case 7: return dispatch_variant<double, true, true, true, false>(m, n, ld, r, t, y, o, params, stream, nd);
+        case 9: return dispatch_variant<double, true, false, false, true>(m, n, ld, r, t, y, o, params, stream, nd);
+        default: return dispatch_variant<double, false, false, false, false>(m, n, ld, r, t, y, o, params, stream, nd);
     }
 }
 

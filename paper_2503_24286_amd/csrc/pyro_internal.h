@@ -176,7 +176,22 @@ struct DevMech {
     const double* comp;                  // [E][S] atoms of element e in species k
 };
 
+// Device tables of a set of transport fits (see the transport kernel).
+struct TransportTables {
+    const double* inv_w;                 // [S] 1/W_k
+    const double* visc;                  // [S][5] viscosity fit b_km
+    const double* cond;                  // [S][5] conductivity fit c_km
+    const double* pair;                  // [S (j)][S (k)][8]: w_kj, v_kj, a_kj0..4, 0
+};
+
 }  // namespace pyro
+
+struct pyro_transport {
+    int device = 0;
+    int S = 0;
+    pyro::TransportTables tt{};
+    void* blob = nullptr;
+};
 
 struct pyro_mech {
     int device = 0;
@@ -222,7 +237,12 @@ hipError_t launch_temperature(const pyro_mech* m, int64_t n, int64_t ld,
                               const double* e, const double* Y,
                               const double* T_guess, double T_guess_value,
                               double* T_out, int32_t* status, int max_iter,
-                              double rtol, hipStream_t stream);
+                              double rtol, hipStream_t stream, bool enthalpy = false);
+hipError_t launch_primitive(const pyro_mech* m, int64_t n, int64_t ld, int dim,
+                            const double* rhok, const double* mom, const double* E,
+                            const double* T_guess, double T_guess_value, double* rho_out,
+                            double* Y_out, double* u_out, double* T_out, double* p_out,
+                            int32_t* status, int max_iter, double rtol, hipStream_t stream);
 hipError_t launch_eos(const pyro_mech* m, int64_t n, int64_t ld, int mode,
                       const double* a, const double* T, const double* Y,
                       double* out, hipStream_t stream);
@@ -231,14 +251,37 @@ hipError_t launch_internal_energy(const pyro_mech* m, int64_t n, int64_t ld,
                                   double* e_out, hipStream_t stream);
 // LDS bytes the production-rate kernel needs for this mechanism.
 size_t production_rates_lds_bytes(const pyro_mech* m, bool reaction_equilibrium,
-                                  bool mfma_third_body = false);
+                                  bool mfma_third_body = false, bool log_space = false,
+                                  int real_bytes = 8);
+// The log-space form (FP64 variant, and every FP32 call) can run this
+// mechanism: one T_mid per reaction and its rows fit the LDS tile.
+bool log_space_supported(const pyro_mech* m, int real_bytes);
 hipError_t prepare_production_rates(const pyro_mech* m);
 hipError_t launch_production_rates_vjp(const pyro_mech* m, int64_t n, int64_t ld,
                                        const double* rho, const double* T, const double* Y,
                                        const double* wbar, double* Ybar, double* Tbar,
                                        double* params_bar, double* wdot,
                                        const double* params, hipStream_t stream);
+// Rows of the chemical Jacobian J[j][k] = dS_j/dY_k (S_j = W_j omega_j),
+// J laid out [S][S][ld]; dSdT ([S][ld]) optional.
+hipError_t launch_chemical_jacobian(const pyro_mech* m, int64_t n, int64_t ld, const double* rho,
+                                    const double* T, const double* Y, int fixed_energy,
+                                    double* J, double* dSdT, const double* params,
+                                    hipStream_t stream);
 size_t vjp_lds_bytes(const pyro_mech* m);
+// Reactor steps (method 0: Runge-Kutta, 1: Crank-Nicolson) and the bytes of
+// workspace they carve.
+size_t reactor_workspace_bytes(const pyro_mech* m, int64_t n, int64_t ld, int method);
+hipError_t launch_rk4_step(const pyro_mech* m, int64_t n, int64_t ld, const double* rho,
+                           const double* e, double* Y, double* T, const double* dt,
+                           double dt_value, int32_t* status, void* ws, hipStream_t s);
+hipError_t launch_cn_step(const pyro_mech* m, int64_t n, int64_t ld, const double* rho,
+                          const double* e, double* Y, double* T, const double* dt,
+                          double dt_value, double tol, int max_iter, int32_t* status, void* ws,
+                          hipStream_t s);
+hipError_t launch_transport(const pyro_mech* m, const TransportTables& tt, int64_t n,
+                            int64_t ld, const double* T, const double* Y, double* mu,
+                            double* kappa, double* D, hipStream_t stream);
 bool nq_supported(const pyro_mech* m);
 hipError_t prepare_vjp(const pyro_mech* m);
 

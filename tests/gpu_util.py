@@ -1,5 +1,7 @@
 """Shared pieces of the GPU tests: device checks and seeded inputs."""
 
+import json
+import os
 import sys
 
 import numpy as np
@@ -22,6 +24,18 @@ def announce(msg):
     capture, before a GPU step."""
     sys.__stderr__.write(f"[gpu-case] {msg}\n")
     sys.__stderr__.flush()
+
+
+def record(case, quantity, value, tol):
+    """Announce an achieved error level and, when PYRO_PARITY_LOG names a
+    file, append it there as one JSON line (case, quantity, value, bar) so
+    that a run's margins can be kept."""
+    announce(f"  {case}: {quantity} {value:.3e} (bar {tol:.0e})")
+    path = os.environ.get("PYRO_PARITY_LOG")
+    if path:
+        with open(path, "a") as f:
+            f.write(json.dumps({"case": case, "quantity": quantity,
+                                "value": float(value), "bar": float(tol)}) + "\n")
 
 
 def states(cfg, n, S, first=0):

@@ -4,7 +4,7 @@ import numpy as np
 import pytest
 
 import mechs
-from gpu_util import announce, states, to_dev, torch_cuda
+from gpu_util import announce, record, states, to_dev, torch_cuda
 from parity import assert_wdot_parity
 from oracle import kinetics
 
@@ -37,7 +37,9 @@ def test_wdot_matches_oracle(lib_mechs, cfg, n):
     announce(f"wdot cfg{cfg} n={n}")
     w = _run(torch, pyro, gms[cfg], rho, T, Y)
     r = assert_wdot_parity(m, rho, T, Y, w)
-    announce(f"  max scaled {r['scaled'].max():.2e}")
+    record(f"wdot cfg{cfg} n={n}", "omega scaled", r["scaled"].max(), 1e-12)
+    well = r["kappa"] <= 1e3
+    record(f"wdot cfg{cfg} n={n}", "omega normwise (kappa <= 1e3)", r["normwise"][well].max(), 1e-12)
 
 
 @pytest.mark.parametrize("n", [1, 2, 63, 64, 65, 127, 129, 200])
@@ -166,7 +168,7 @@ def test_both_equilibrium_variants_match_oracle(lib_mechs, cfg, n):
             announce(f"wdot variant {variant} cfg{cfg} n={n}")
             w = _run(torch, pyro, gm, rho, T, Y)
             r = assert_wdot_parity(m, rho, T, Y, w)
-            announce(f"  max scaled {r['scaled'].max():.2e}")
+            record(f"wdot variant {variant} cfg{cfg} n={n}", "omega scaled", r["scaled"].max(), 1e-12)
     finally:
         gm.wdot_variant = before
 
@@ -185,7 +187,7 @@ def test_large_mechanism_matches_oracle(cfg3_mech, n):
     announce(f"wdot cfg3 n={n}")
     w = _run(torch, pyro, gm, rho, T, Y)
     r = assert_wdot_parity(m, rho, T, Y, w)
-    announce(f"  max scaled {r['scaled'].max():.2e}")
+    record(f"wdot cfg3 n={n}", "omega scaled", r["scaled"].max(), 1e-12)
     with pytest.raises(_lib.PyroError) as e:
         gm.wdot_variant = _lib.PYRO_WDOT_REACTION_EQUILIBRIUM | _lib.PYRO_WDOT_MFMA_THIRD_BODY
     assert e.value.code == _lib.PYRO_E_UNSUPPORTED
@@ -201,10 +203,114 @@ def test_variant_selection_errors(cfg3_mech):
     with pytest.raises(_lib.PyroError) as e:   # more than 64 species
         gm.wdot_variant = _lib.PYRO_WDOT_REACTION_EQUILIBRIUM | _lib.PYRO_WDOT_MFMA_NET_RATES
     assert e.value.code == _lib.PYRO_E_UNSUPPORTED
+    with pytest.raises(_lib.PyroError) as e:   # 160 (C, ln C) rows exceed the LDS
+        gm.wdot_variant = _lib.PYRO_WDOT_LOG_SPACE
+    assert e.value.code == _lib.PYRO_E_UNSUPPORTED
     with pytest.raises(_lib.PyroError) as e:
-        gm.wdot_variant = 8
+        gm.wdot_variant = 16
     assert e.value.code == _lib.PYRO_E_ARG
     with pytest.raises(_lib.PyroError) as e:
         gm.wdot_variant = -1
     assert e.value.code == _lib.PYRO_E_ARG
     assert gm.wdot_variant == _lib.PYRO_WDOT_REACTION_EQUILIBRIUM
+
+
+@pytest.mark.parametrize("cfg,n", [(0, 1000), (1, 2000 + 45)])
+def test_log_space_variant_matches_oracle(lib_mechs, cfg, n):
+    """The log-space form (each rate one exponential of ln k plus sums of
+    nu ln C) at the FP64 parity bar, with degenerate states: zero and
+    negative mass fractions (ln C = -inf), a pure species, T at T_mid."""
+    from paper_2503_24286_amd import _lib
+    torch, pyro, gms = lib_mechs
+    m = mechs.load_config(cfg)
+    gm = gms[cfg]
+    T, p, Y, rho = states(cfg, n, m.S, first=3333)
+    Y[:, :32] = 0.0
+    Y[min(5, m.S - 1), :32] = 1.0
+    Y[3, 32:64] = -1e-3
+    T[64:72] = m.T_mid[0]
+    before = gm.wdot_variant
+    try:
+        gm.wdot_variant = _lib.PYRO_WDOT_LOG_SPACE
+        assert gm.wdot_variant == _lib.PYRO_WDOT_LOG_SPACE | _lib.PYRO_WDOT_REACTION_EQUILIBRIUM
+        announce(f"wdot log-space cfg{cfg} n={n}")
+        w = _run(torch, pyro, gm, rho, T, Y)
+        r = assert_wdot_parity(m, rho, T, Y, w)
+        record(f"wdot log-space cfg{cfg} n={n}", "omega scaled", r["scaled"].max(), 1e-12)
+        for bad in (_lib.PYRO_WDOT_LOG_SPACE | _lib.PYRO_WDOT_MFMA_THIRD_BODY,
+                    _lib.PYRO_WDOT_LOG_SPACE | _lib.PYRO_WDOT_MFMA_NET_RATES):
+            with pytest.raises(_lib.PyroError):
+                gm.wdot_variant = bad
+    finally:
+        gm.wdot_variant = before
+
+
+# FP32: the stated bar is 1e-4 of the summed terms' magnitudes per species,
+# floored at 1e-36 (results below the float normal range keep few digits)
+TOL_F32 = 1e-4
+F32_FLOOR = 1e-36
+F32_MAX = float(np.finfo(np.float32).max)
+
+
+def fp32_classes(m, rho, T, Y):
+    """Per cell, from the oracle's FP64 rates: 'safe' when every partial sum
+    of the species gathering stays below half the float range (no result can
+    overflow), 'over' when some rate exceeds twice the float range (the
+    log-space kernel must return a non-finite omega), else undecided."""
+    Rf, Rr, phi, q = kinetics.rates_of_progress(m, rho, T, Y)
+    mag = np.abs(m.nu) @ ((np.abs(Rf) + np.abs(Rr)) * np.abs(phi))
+    big = np.maximum(np.abs(Rf), np.abs(Rr)) * np.abs(phi)
+    safe = mag.max(axis=0) < 0.5 * F32_MAX
+    over = big.max(axis=0) > 2.0 * F32_MAX
+    return safe, over, mag
+
+
+@pytest.mark.parametrize("cfg,n", [(0, 4096), (1, 4096 + 37)])
+def test_fp32_matches_oracle(lib_mechs, cfg, n):
+    """PYRO_F32 against the FP64 oracle on the same (float-rounded) inputs:
+    cells whose rates fit the float range are finite and within 1e-4 scaled;
+    cells with a rate beyond it come back non-finite (counted)."""
+    torch, pyro, gms = lib_mechs
+    m = mechs.load_config(cfg)
+    T, p, Y, rho = states(cfg, n, m.S, first=2024)
+    T32, r32, Y32 = (a.astype(np.float32) for a in (T, rho, Y))
+    T, rho, Y = (a.astype(np.float64) for a in (T32, r32, Y32))
+    announce(f"wdot fp32 cfg{cfg} n={n}")
+    r, t, y = to_dev(torch, r32, T32, Y32)
+    w = pyro.production_rates(gms[cfg], r, t, y)
+    torch.cuda.synchronize()
+    assert w.dtype == torch.float32
+    w = w.cpu().numpy().astype(np.float64)
+    safe, over, mag = fp32_classes(m, rho, T, Y)
+    w_ref = kinetics.net_production_rates(m, rho, T, Y)
+    finite = np.isfinite(w).all(axis=0)
+    assert np.all(finite[safe]), f"{np.sum(~finite[safe])} in-range cells are not finite"
+    assert not np.any(finite[over]), f"{np.sum(finite[over])} overflowing cells came back finite"
+    err = (np.abs(w - w_ref) / np.maximum(mag, F32_FLOOR))[:, safe].max(axis=0)
+    case = f"wdot fp32 cfg{cfg} n={n}"
+    record(case, "omega scaled (in-range cells)", err.max(), TOL_F32)
+    record(case, "fraction of cells with a rate beyond the float range", over.mean(), 1.0)
+    record(case, "fraction undecided (near the float limit)", (~safe & ~over).mean(), 1.0)
+    assert err.max() <= TOL_F32, f"scaled error {err.max():.3e} at cell {np.argmax(err)}"
+
+
+def test_fp32_ragged_and_padded(lib_mechs):
+    torch, pyro, gms = lib_mechs
+    m = mechs.load_config(1)
+    n = 129
+    T, p, Y, rho = states(1, n, m.S, first=31)
+    ld = n + 11
+    announce("wdot fp32 ragged/padded")
+    Yb = torch.full((m.S, ld), float("nan"), dtype=torch.float32, device="cuda")
+    Yb[:, :n] = torch.from_numpy(Y.astype(np.float32)).cuda()
+    out = torch.full((m.S, ld), -3.0, dtype=torch.float32, device="cuda")
+    r, t = to_dev(torch, rho.astype(np.float32), T.astype(np.float32))
+    pyro.production_rates(gms[1], r, t, Yb[:, :n], out=out[:, :n])
+    torch.cuda.synchronize()
+    o = out.cpu().numpy()
+    assert np.all(o[:, n:] == -3.0)
+    w_ref = _run(torch, pyro, gms[1], rho.astype(np.float32).astype(float),
+                 T.astype(np.float32).astype(float), Y.astype(np.float32).astype(float))
+    fin = np.isfinite(o[:, :n]).all(axis=0)
+    scale = np.abs(w_ref).max(axis=0)
+    assert np.all((np.abs(o[:, :n] - w_ref).max(axis=0) <= 1e-3 * scale)[fin])
