@@ -200,6 +200,27 @@ PYRO_API int pyro_production_rates_vjp(const pyro_mech* mech, int64_t n, int64_t
                                        double* wdot, const double* params, void* stream);
 
 /*
+ * pyro_production_rates_vjp without any allocation, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, results (bitwise) and
+ * errors as pyro_production_rates_vjp, except: the per-workgroup parameter
+ * partials live in a fixed device array of 2^19 doubles (4 MiB) that each
+ * device holds from the first mechanism load on it until the process ends,
+ * so the call returns PYRO_E_UNSUPPORTED when min(ceil(n/64), compute
+ * units) x 3 (R + n_falloff) exceeds 2^19 (about 680 Arrhenius triples on a
+ * 256-CU device), and it makes no hipMalloc, hipFree or memset (n == 0 zeroes
+ * params_bar with a kernel).  Every call on one device shares that array:
+ * calls that overlap in time on one device (other streams, other threads)
+ * race and give wrong parameter gradients; calls on one stream are ordered.
+ */
+PYRO_API int pyro_production_rates_vjp_noalloc(const pyro_mech* mech, int64_t n, int64_t ld,
+                                               const double* rho, const double* T,
+                                               const double* Y, const double* wbar,
+                                               double* Ybar, double* Tbar, double* params_bar,
+                                               double* wdot, const double* params,
+                                               void* stream);
+
+/*
  * Chemical Jacobian J = dS/dY of the source terms S_j = W_j omega_j
  * (eq. jacobian and eq. chem_jacobian, Sec. "Automatic Differentiation
  * Enables Implicit Time Marching"; eq. massfrac_ode defines S), per cell, at

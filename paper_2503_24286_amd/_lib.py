@@ -61,6 +61,8 @@ SIGNATURES = {
     "pyro_production_rates_vjp": (_I, [_P, _I64, _I64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "pyro_temperature": (_I, [_P, _I64, _I64, _P, _P, _P, _D, _P, _P, _I, _D, _P]),
     "pyro_chemical_jacobian": (_I, [_P, _I64, _I64, _P, _P, _P, _I, _P, _P, _P, _P]),
+    "pyro_production_rates_vjp_noalloc": (_I, [_P, _I64, _I64, _P, _P, _P, _P, _P, _P, _P, _P,
+                                               _P, _P]),
     "pyro_temperature_from_enthalpy": (_I, [_P, _I64, _I64, _P, _P, _P, _D, _P, _P, _I, _D, _P]),
     "pyro_primitive_from_conserved": (_I, [_P, _I64, _I64, _I, _P, _P, _P, _P, _D, _P, _P, _P,
                                            _P, _P, _P, _I, _D, _P]),

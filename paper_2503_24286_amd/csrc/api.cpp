@@ -1,5 +1,6 @@
 // C ABI of libpyro (include/pyro.h): argument validation, error reporting
 // and dispatch to the kernel launchers.
+#include <algorithm>
 #include <cmath>
 #include <string>
 #include <vector>
@@ -175,6 +176,34 @@ int pyro_production_rates_vjp(const pyro_mech* m, int64_t n, int64_t ld, const d
     return launched(launch_production_rates_vjp(m, n, ld, rho, T, Y, wbar, Ybar, Tbar, params_bar,
                                                 wdot, params, s),
                     "VJP kernel launch");
+}
+
+int pyro_production_rates_vjp_noalloc(const pyro_mech* m, int64_t n, int64_t ld,
+                                      const double* rho, const double* T, const double* Y,
+                                      const double* wbar, double* Ybar, double* Tbar,
+                                      double* params_bar, double* wdot, const double* params,
+                                      void* stream) {
+    clear_error();
+    if (int rc = check_sizes(n, ld)) return rc;
+    if (int rc = check_mech(m)) return rc;
+    if (!params_bar) return fail(PYRO_E_ARG, "null pointer: params_bar");
+    if (vjp_lds_bytes(m) > 160 * 1024)
+        return fail(PYRO_E_UNSUPPORTED, "mechanism too large for the VJP tile");
+    if (m->vjp_max_own > 16) return fail(PYRO_E_UNSUPPORTED, "too many species for the VJP kernel");
+    const size_t need = size_t(vjp_scratch_blocks(m, std::max<int64_t>(n, 1))) * 3 *
+                        size_t(m->R + m->n_fo);
+    if (need > kVjpScratchDoubles)
+        return fail(PYRO_E_UNSUPPORTED,
+                    "the parameter partials (" + std::to_string(need) +
+                        " doubles) exceed the fixed scratch of " +
+                        std::to_string(kVjpScratchDoubles) + " doubles");
+    if (n > 0)
+        if (int rc = check_ptrs({rho, T, Y, wbar, Ybar, Tbar}, "rho, T, Y, wbar, Ybar and Tbar"))
+            return rc;
+    return launched(launch_production_rates_vjp_noalloc(m, n, ld, rho, T, Y, wbar, Ybar, Tbar,
+                                                        params_bar, wdot, params,
+                                                        static_cast<hipStream_t>(stream)),
+                    "allocation-free VJP launch");
 }
 
 int pyro_chemical_jacobian(const pyro_mech* m, int64_t n, int64_t ld, const double* rho,

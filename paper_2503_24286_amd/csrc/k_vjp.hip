@@ -24,6 +24,7 @@
 // second kernel adds the per-workgroup accumulators in a fixed order, so the
 // results are bitwise reproducible.
 #include <algorithm>
+#include <mutex>
 
 #include "pyro_internal.h"
 
@@ -671,7 +672,86 @@ hipError_t launch_jacobian_mode(const pyro_mech* m, int64_t n, int64_t ld, const
     return launch_jacobian_own<16, JAC>(m, n, ld, rho, T, Y, J, dSdT, params, stream);
 }
 
+// zeroes n doubles (a kernel rather than a memset node, for callers that
+// capture the call in a graph)
+__global__ void fill_zero_kernel(int n, double* __restrict__ out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = 0.0;
+}
+
+hipError_t launch_vjp_with(const pyro_mech* m, int64_t n, int64_t ld, const double* rho,
+                           const double* T, const double* Y, const double* wbar, double* Ybar,
+                           double* Tbar, double* params_bar, double* wdot, const double* params,
+                           double* partial, int blocks, hipStream_t stream) {
+    const int rows3 = 3 * (m->R + m->n_fo);
+    const VjpArgs a{blocks, n, ld, rho, T, Y, wbar, Ybar, Tbar, wdot, partial,
+                    params ? params : m->dev.params};
+    hipError_t e;
+    if (m->vjp_max_own <= 4)
+        e = launch_vjp_own<4>(m, a, stream);
+    else if (m->vjp_max_own <= 8)
+        e = launch_vjp_own<8>(m, a, stream);
+    else
+        e = launch_vjp_own<16>(m, a, stream);
+    if (e == hipSuccess && rows3 > 0) {
+        hipLaunchKernelGGL(vjp_reduce_kernel, dim3((rows3 + 255) / 256), dim3(256), 0, stream,
+                           rows3, blocks, a.partial, params_bar);
+        e = hipGetLastError();
+    }
+    return e;
+}
+
+// The allocation-free entry point's scratch: the per-workgroup parameter
+// partials live in this fixed array, one copy per device, its address looked
+// up once per device when a mechanism is loaded there.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
 }  // namespace
+
+// The fixed device array itself (host code uses the address looked up per
+// device, never this name: in host code it is only a stand-in symbol).
+static __device__ __align__(256) double scratch[kVjpScratchDoubles];
+
+hipError_t vjp_scratch_init(int device) {
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[device]) return hipSuccess;
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[device] = static_cast<double*>(p);
+    return hipSuccess;
+}
+
+int vjp_scratch_blocks(const pyro_mech* m, int64_t n) {
+    const int64_t n_tiles = (n + kTile - 1) / kTile;
+    return int(std::min<int64_t>(n_tiles, int64_t(m->n_cu)));
+}
+
+hipError_t launch_production_rates_vjp_noalloc(const pyro_mech* m, int64_t n, int64_t ld,
+                                               const double* rho, const double* T,
+                                               const double* Y, const double* wbar,
+                                               double* Ybar, double* Tbar, double* params_bar,
+                                               double* wdot, const double* params,
+                                               hipStream_t stream) {
+    double* ptr = nullptr;   // this device's copy of the scratch array
+    {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        if (m->device >= 0 && m->device < kMaxDevices) ptr = g_scratch_ptr[m->device];
+    }
+    if (!ptr) return hipErrorNotInitialized;
+    const int rows3 = 3 * (m->R + m->n_fo);
+    if (n == 0) {
+        if (rows3 > 0)
+            hipLaunchKernelGGL(fill_zero_kernel, dim3((rows3 + 255) / 256), dim3(256), 0, stream,
+                               rows3, params_bar);
+        return hipGetLastError();
+    }
+    return launch_vjp_with(m, n, ld, rho, T, Y, wbar, Ybar, Tbar, params_bar, wdot, params,
+                           ptr, vjp_scratch_blocks(m, n), stream);
+}
 
 hipError_t launch_chemical_jacobian(const pyro_mech* m, int64_t n, int64_t ld, const double* rho,
                                     const double* T, const double* Y, int fixed_energy,
@@ -689,6 +769,9 @@ size_t vjp_lds_bytes(const pyro_mech* m) {
 }
 
 hipError_t prepare_vjp(const pyro_mech* m) {
+    // the allocation-free entry point's scratch address on this device
+    const hipError_t es = vjp_scratch_init(m->device);
+    if (es != hipSuccess) return es;
     const size_t bytes = vjp_lds_bytes(m);
     if (bytes > 160 * 1024) return hipSuccess;  // the VJP call reports it as unsupported
     const int lds = int(bytes);
@@ -704,26 +787,14 @@ hipError_t launch_production_rates_vjp(const pyro_mech* m, int64_t n, int64_t ld
                                        const double* wbar, double* Ybar, double* Tbar,
                                        double* params_bar, double* wdot, const double* params,
                                        hipStream_t stream) {
-    const int64_t n_tiles = (n + kTile - 1) / kTile;
-    const int blocks = int(std::min<int64_t>(n_tiles, int64_t(m->n_cu)));
+    const int blocks = vjp_scratch_blocks(m, n);
     const int rows3 = 3 * (m->R + m->n_fo);
     const size_t pbytes = size_t(blocks) * rows3 * sizeof(double);
     void* partial = nullptr;
     hipError_t e = hipMallocAsync(&partial, pbytes > 0 ? pbytes : 8, stream);
     if (e != hipSuccess) return e;
-    const VjpArgs a{blocks, n, ld, rho, T, Y, wbar, Ybar, Tbar, wdot,
-                    static_cast<double*>(partial), params ? params : m->dev.params};
-    if (m->vjp_max_own <= 4)
-        e = launch_vjp_own<4>(m, a, stream);
-    else if (m->vjp_max_own <= 8)
-        e = launch_vjp_own<8>(m, a, stream);
-    else
-        e = launch_vjp_own<16>(m, a, stream);
-    if (e == hipSuccess && rows3 > 0) {
-        hipLaunchKernelGGL(vjp_reduce_kernel, dim3((rows3 + 255) / 256), dim3(256), 0, stream,
-                           rows3, blocks, a.partial, params_bar);
-        e = hipGetLastError();
-    }
+    e = launch_vjp_with(m, n, ld, rho, T, Y, wbar, Ybar, Tbar, params_bar, wdot, params,
+                        static_cast<double*>(partial), blocks, stream);
     const hipError_t ef = hipFreeAsync(partial, stream);
     return e != hipSuccess ? e : ef;
 }

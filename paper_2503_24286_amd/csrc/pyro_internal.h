@@ -269,6 +269,16 @@ hipError_t launch_chemical_jacobian(const pyro_mech* m, int64_t n, int64_t ld, c
                                     double* J, double* dSdT, const double* params,
                                     hipStream_t stream);
 size_t vjp_lds_bytes(const pyro_mech* m);
+// Fixed scratch of the allocation-free VJP (per-workgroup parameter partials).
+constexpr size_t kVjpScratchDoubles = size_t(1) << 19;    // 4 MiB
+hipError_t vjp_scratch_init(int device);
+int vjp_scratch_blocks(const pyro_mech* m, int64_t n);
+hipError_t launch_production_rates_vjp_noalloc(const pyro_mech* m, int64_t n, int64_t ld,
+                                               const double* rho, const double* T,
+                                               const double* Y, const double* wbar,
+                                               double* Ybar, double* Tbar, double* params_bar,
+                                               double* wdot, const double* params,
+                                               hipStream_t stream);
 // Reactor steps (method 0: Runge-Kutta, 1: Crank-Nicolson) and the bytes of
 // workspace they carve.
 size_t reactor_workspace_bytes(const pyro_mech* m, int64_t n, int64_t ld, int method);
