@@ -87,7 +87,8 @@ def _cfg0_state(n=6, first=40):
     e = thermo.mixture_internal_energy(m, T, Y)
     f, _ = reactor.rhs(m, rho, e, Y, T)
     # a step well inside the fastest local time scale of each cell
-    tau = np.min(np.where(np.abs(f) > 0, np.maximum(Y, 1e-3) / np.abs(f), np.inf), axis=0)
+    with np.errstate(divide="ignore"):
+        tau = np.min(np.where(np.abs(f) > 0, np.maximum(Y, 1e-3) / np.abs(f), np.inf), axis=0)
     return m, rho, e, T, Y, 0.05 * tau
 
 
