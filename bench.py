@@ -303,6 +303,15 @@ def large_mechanism_leg(args, log):
         ms_mfma = _time_ms(lambda: pyro.production_rates(gm, rho, Td, Yd, out=w), args.reps, stream)
     except _lib.PyroError:   # its [M] block does not fit beside this mechanism's tile
         ms_mfma = None
+    # the net rates omega = nu q on the FP64 matrix cores (dense nu, ten
+    # 16-species blocks) instead of the sparse gathering
+    try:
+        gm.wdot_variant = base | _lib.PYRO_WDOT_MFMA_NET_RATES
+        ms_nq = _time_ms(lambda: pyro.production_rates(gm, rho, Td, Yd, out=w), args.reps, stream)
+        if not bool(torch.isfinite(w).all()):
+            raise RuntimeError("non-finite rates on the large mechanism (MFMA net rates)")
+    except _lib.PyroError:
+        ms_nq = None
     gm.wdot_variant = base
     fpc = wdot_flops_per_cell(gm)
     achieved = fpc * n / (ms * 1e-3) / 1e12
@@ -311,6 +320,7 @@ def large_mechanism_leg(args, log):
                        else "species-equilibrium",
            "ms": round(ms, 4), "Mcells_s": round(n / ms / 1e3, 3), "flops_per_cell": fpc,
            "third_body_on_mfma_ms": None if ms_mfma is None else round(ms_mfma, 4),
+           "net_rates_on_mfma_ms": None if ms_nq is None else round(ms_nq, 4),
            "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS,
                         "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4)}}
     log(f"large mechanism: {out['Mcells_s']} Mcells/s")

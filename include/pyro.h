@@ -81,7 +81,8 @@ enum pyro_wdot_variant {
      * omega = nu q (eq. production_rates) of a 64-cell tile accumulated on
      * the FP64 matrix cores over the reaction chunks with the dense nu
      * (v_mfma_f64_16x16x4f64), instead of the sparse per-species gathering;
-     * at most 64 species */
+     * at most 64 species, or 192 for mechanisms large enough to run the
+     * 16-wavefront schedule */
     PYRO_WDOT_MFMA_NET_RATES = 4,
     /* log-space form (implies the reaction-equilibrium coefficients, no
      * matrix-core flags): each rate is one exponential of a sum of logarithms,

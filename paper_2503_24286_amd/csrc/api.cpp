@@ -117,7 +117,8 @@ int pyro_mech_set_wdot_variant(pyro_mech* m, int variant) {
     if (rkc && !m->kc_ok)
         return fail(PYRO_E_UNSUPPORTED, "reactions mix species with different NASA7 T_mid");
     if (nq && !nq_supported(m))
-        return fail(PYRO_E_UNSUPPORTED, "the matrix-core net rates need at most 64 species");
+        return fail(PYRO_E_UNSUPPORTED, "the matrix-core net rates need at most 64 species (192 "
+                                        "with the 16-wavefront schedule of large mechanisms)");
     if (production_rates_lds_bytes(m, rkc, mm) > 160 * 1024)
         return fail(PYRO_E_UNSUPPORTED, rkc ? "mechanism too large for the LDS tile"
                                             : "species rows of this mechanism exceed the LDS tile");

@@ -275,13 +275,16 @@ __device__ inline double cp_poly(const double* a, double T) {
 // dS_unit/dT; reactions without species ``unit`` have a zero cotangent and
 // are skipped, and no parameter sums are formed.  JAC == 2 adds the
 // dependence of T on Y at fixed internal energy, dT/dY_k = -e_k/c_v.
-template <int MAXOWN, int MAXPD, bool WITH_W, int JAC = 0>
+// LNT: ln T comes from lnTg (a pre-pass) instead of a logarithm per tile;
+// keeping the logarithm's constants live across the persistent tile loop
+// spilled them to scratch, reloaded on every tile.
+template <int MAXOWN, int MAXPD, bool WITH_W, int JAC = 0, bool LNT = false>
 __global__ __launch_bounds__(kVjpWaves * 64) void vjp_kernel(
     DevMech m, int64_t n, int64_t ld, const double* __restrict__ rho,
     const double* __restrict__ T, const double* __restrict__ Y,
     const double* __restrict__ wbar, double* __restrict__ Ybar, double* __restrict__ Tbar,
     double* __restrict__ wdot, double* __restrict__ partial, const double* __restrict__ params,
-    int unit = -1) {
+    int unit = -1, const double* __restrict__ lnTg = nullptr) {
     static_assert(JAC == 0 || !WITH_W, "Jacobian rows do not return omega");
     constexpr int kBuf = (WITH_W ? 3 : 2) * kPlane;   // one chunk buffer: a, b (, q) planes
     extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
@@ -313,7 +316,11 @@ __global__ __launch_bounds__(kVjpWaves * 64) void vjp_kernel(
         CellState cs;
         cs.T = T[c];
         const double rc = rho[c];
-        cs.lnT = log(cs.T);
+        if constexpr (LNT) {
+            cs.lnT = lnTg[c];
+        } else {
+            cs.lnT = log(cs.T);
+        }
         cs.invT = 1.0 / cs.T;
         const double omlnT = 1.0 - cs.lnT;
 
@@ -570,6 +577,13 @@ __global__ __launch_bounds__(kVjpWaves * 64) void vjp_kernel(
     }
 }
 
+// ln T of every cell, read by the reverse sweep's LNT instances
+__global__ void log_temperature_kernel(int64_t n, const double* __restrict__ T,
+                                       double* __restrict__ out) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = log(T[i]);
+}
+
 // pbar[row][f] = sum over workgroups of their sums, in workgroup order.
 __global__ void vjp_reduce_kernel(int rows3, int blocks, const double* __restrict__ partial,
                                   double* __restrict__ pbar) {
@@ -580,10 +594,10 @@ __global__ void vjp_reduce_kernel(int rows3, int blocks, const double* __restric
     pbar[idx] = s;
 }
 
-template <int MAXOWN, int MAXPD, bool WITH_W, int JAC = 0>
+template <int MAXOWN, int MAXPD, bool WITH_W, int JAC = 0, bool LNT = false>
 hipError_t set_lds_vjp(int bytes) {
     return hipFuncSetAttribute(
-        reinterpret_cast<const void*>(&vjp_kernel<MAXOWN, MAXPD, WITH_W, JAC>),
+        reinterpret_cast<const void*>(&vjp_kernel<MAXOWN, MAXPD, WITH_W, JAC, LNT>),
         hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
@@ -593,20 +607,27 @@ struct VjpArgs {
     const double *rho, *T, *Y, *wbar;
     double *Ybar, *Tbar, *wdot, *partial;
     const double* params;
+    const double* lnT;     // ln T per cell, or NULL to evaluate it per tile
 };
+
+template <int MAXOWN, int MAXPD, bool LNT>
+hipError_t launch_vjp_lnt(const pyro_mech* m, const VjpArgs& a, hipStream_t stream) {
+    const size_t lds = vjp_lds_bytes(m);
+    if (a.wdot)
+        hipLaunchKernelGGL((vjp_kernel<MAXOWN, MAXPD, true, 0, LNT>), dim3(unsigned(a.blocks)),
+                           dim3(kVjpWaves * 64), lds, stream, m->dev, a.n, a.ld, a.rho, a.T, a.Y,
+                           a.wbar, a.Ybar, a.Tbar, a.wdot, a.partial, a.params, -1, a.lnT);
+    else
+        hipLaunchKernelGGL((vjp_kernel<MAXOWN, MAXPD, false, 0, LNT>), dim3(unsigned(a.blocks)),
+                           dim3(kVjpWaves * 64), lds, stream, m->dev, a.n, a.ld, a.rho, a.T, a.Y,
+                           a.wbar, a.Ybar, a.Tbar, a.wdot, a.partial, a.params, -1, a.lnT);
+    return hipGetLastError();
+}
 
 template <int MAXOWN, int MAXPD>
 hipError_t launch_vjp(const pyro_mech* m, const VjpArgs& a, hipStream_t stream) {
-    const size_t lds = vjp_lds_bytes(m);
-    if (a.wdot)
-        hipLaunchKernelGGL((vjp_kernel<MAXOWN, MAXPD, true>), dim3(unsigned(a.blocks)),
-                           dim3(kVjpWaves * 64), lds, stream, m->dev, a.n, a.ld, a.rho, a.T, a.Y,
-                           a.wbar, a.Ybar, a.Tbar, a.wdot, a.partial, a.params);
-    else
-        hipLaunchKernelGGL((vjp_kernel<MAXOWN, MAXPD, false>), dim3(unsigned(a.blocks)),
-                           dim3(kVjpWaves * 64), lds, stream, m->dev, a.n, a.ld, a.rho, a.T, a.Y,
-                           a.wbar, a.Ybar, a.Tbar, a.wdot, a.partial, a.params);
-    return hipGetLastError();
+    return a.lnT ? launch_vjp_lnt<MAXOWN, MAXPD, true>(m, a, stream)
+                 : launch_vjp_lnt<MAXOWN, MAXPD, false>(m, a, stream);
 }
 
 template <int MAXOWN>
@@ -623,6 +644,9 @@ hipError_t set_lds_own(int bytes) {
         set_lds_vjp<MAXOWN, 4, false>(bytes), set_lds_vjp<MAXOWN, 8, false>(bytes),
         set_lds_vjp<MAXOWN, 16, false>(bytes), set_lds_vjp<MAXOWN, 4, true>(bytes),
         set_lds_vjp<MAXOWN, 8, true>(bytes), set_lds_vjp<MAXOWN, 16, true>(bytes),
+        set_lds_vjp<MAXOWN, 4, false, 0, true>(bytes), set_lds_vjp<MAXOWN, 8, false, 0, true>(bytes),
+        set_lds_vjp<MAXOWN, 16, false, 0, true>(bytes), set_lds_vjp<MAXOWN, 4, true, 0, true>(bytes),
+        set_lds_vjp<MAXOWN, 8, true, 0, true>(bytes), set_lds_vjp<MAXOWN, 16, true, 0, true>(bytes),
         set_lds_vjp<MAXOWN, 4, false, 1>(bytes), set_lds_vjp<MAXOWN, 8, false, 1>(bytes),
         set_lds_vjp<MAXOWN, 16, false, 1>(bytes), set_lds_vjp<MAXOWN, 4, false, 2>(bytes),
         set_lds_vjp<MAXOWN, 8, false, 2>(bytes), set_lds_vjp<MAXOWN, 16, false, 2>(bytes)};
@@ -682,10 +706,17 @@ __global__ void fill_zero_kernel(int n, double* __restrict__ out) {
 hipError_t launch_vjp_with(const pyro_mech* m, int64_t n, int64_t ld, const double* rho,
                            const double* T, const double* Y, const double* wbar, double* Ybar,
                            double* Tbar, double* params_bar, double* wdot, const double* params,
-                           double* partial, int blocks, hipStream_t stream) {
+                           double* partial, int blocks, hipStream_t stream,
+                           double* lnT = nullptr) {
     const int rows3 = 3 * (m->R + m->n_fo);
+    if (lnT) {
+        hipLaunchKernelGGL(log_temperature_kernel, dim3(unsigned((n + 255) / 256)), dim3(256), 0,
+                           stream, n, T, lnT);
+        const hipError_t e0 = hipGetLastError();
+        if (e0 != hipSuccess) return e0;
+    }
     const VjpArgs a{blocks, n, ld, rho, T, Y, wbar, Ybar, Tbar, wdot, partial,
-                    params ? params : m->dev.params};
+                    params ? params : m->dev.params, lnT};
     hipError_t e;
     if (m->vjp_max_own <= 4)
         e = launch_vjp_own<4>(m, a, stream);
@@ -789,12 +820,14 @@ hipError_t launch_production_rates_vjp(const pyro_mech* m, int64_t n, int64_t ld
                                        hipStream_t stream) {
     const int blocks = vjp_scratch_blocks(m, n);
     const int rows3 = 3 * (m->R + m->n_fo);
-    const size_t pbytes = size_t(blocks) * rows3 * sizeof(double);
+    // workspace: the per-workgroup parameter partials, then ln T per cell
+    const size_t pbytes = (size_t(blocks) * rows3 + size_t(n)) * sizeof(double);
     void* partial = nullptr;
     hipError_t e = hipMallocAsync(&partial, pbytes > 0 ? pbytes : 8, stream);
     if (e != hipSuccess) return e;
-    e = launch_vjp_with(m, n, ld, rho, T, Y, wbar, Ybar, Tbar, params_bar, wdot, params,
-                        static_cast<double*>(partial), blocks, stream);
+    double* pd = static_cast<double*>(partial);
+    e = launch_vjp_with(m, n, ld, rho, T, Y, wbar, Ybar, Tbar, params_bar, wdot, params, pd,
+                        blocks, stream, pd + size_t(blocks) * rows3);
     const hipError_t ef = hipFreeAsync(partial, stream);
     return e != hipSuccess ? e : ef;
 }

@@ -337,7 +337,6 @@ __global__ __launch_bounds__(WAVES * 64) void wdot_kernel(
 
     unsigned char* qbase = lds + size_t(m.S) * rowb;
     constexpr int qbuf = WAVES * kRxnPerWave * kTile * sizeof(real);   // bytes per chunk buffer
-    static_assert(!NQ || WAVES == kWaves, "the MFMA net rates assume kWaves wavefronts");
     double* Ml = reinterpret_cast<double*>(qbase + 2 * qbuf);  // MM: [n_pd16][64]
     if constexpr (MM) {
         // ---- the tile's third-body concentrations on the matrix cores: wave w
@@ -379,23 +378,36 @@ __global__ __launch_bounds__(WAVES * 64) void wdot_kernel(
 #pragma unroll
     for (int i = 0; i < (NQ ? 1 : MAXOWN); ++i) acc[i] = real(0);
     // NQ: omega[64 cells x S] accumulated on the matrix cores over the chunks,
-    // omega += q[cells x 16 slots] nu[16 slots x S]; wave w holds the
-    // 16-cell x 16-species output blocks (cell block w & 3, species blocks
-    // (w >> 2) and (w >> 2) + 2)
+    // omega += q[cells x K slots] nu[K slots x S] with K = 2 WAVES; wave w
+    // holds the 16-cell x 16-species output blocks of cell block w & 3 and
+    // species blocks (w >> 2) + b WAVES/4, b < NQB (those below ceil(S/16))
+    constexpr int NQB = WAVES == kWaves ? 2 : 3;    // S <= 64 (8 waves), <= 192 (16)
+    constexpr int NKS = WAVES * kRxnPerWave / 4;     // K-steps per chunk
+    // species blocks held in the fragment table: four with kWaves wavefronts
+    // (zero-filled beyond S, so every block multiplies unconditionally)
     const int nq_cb = w & 3, nq_sb = w >> 2;
-    d4 wacc[2] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
+    const int nq_nsb = WAVES == kWaves ? 4 : (m.S + 15) / 16;
+    d4 wacc[NQB];
+#pragma unroll
+    for (int b = 0; b < NQB; ++b) wacc[b] = d4{0.0, 0.0, 0.0, 0.0};
     static_assert(kRxnPerWave == 2, "the reaction phase handles reactions in pairs");
     for (int ch = 0; ch < m.n_chunks; ++ch) {
         unsigned char* qb = qbase + (ch & 1) * qbuf;
-        // NQ: this chunk's B fragments of nu, loaded before the rates are evaluated
-        double nub[2][4];
-        if constexpr (NQ) {
+        // NQ: this chunk's B fragments of nu, [chunk][species block][K-step][lane]
+        double nub[NQB][NKS];
+        auto load_nub = [&]() {
 #pragma unroll
-            for (int b = 0; b < 2; ++b)
+            for (int b = 0; b < NQB; ++b) {
+                const int sb = nq_sb + b * (WAVES / 4);
 #pragma unroll
-                for (int kk = 0; kk < 4; ++kk)
-                    nub[b][kk] = m.nu_frag[((size_t(ch) * 4 + nq_sb + 2 * b) * 4 + kk) * 64 + lane];
-        }
+                for (int kk = 0; kk < NKS; ++kk)
+                    nub[b][kk] = (WAVES == kWaves || sb < nq_nsb)
+                        ? m.nu_frag[((size_t(ch) * nq_nsb + sb) * NKS + kk) * 64 + lane] : 0.0;
+            }
+        };
+        // (8 waves: loaded before the rates are evaluated; 16 waves, with
+        // three blocks of eight K-steps, after them to spare registers)
+        if constexpr (NQ && WAVES == kWaves) load_nub();
         const RxnRec* rb = m.rxn + (size_t(ch) * WAVES + w) * kRxnPerWave;
         const RxnRec r0 = rb[0];
         const RxnRec r1 = rb[1];
@@ -438,16 +450,18 @@ __global__ __launch_bounds__(WAVES * 64) void wdot_kernel(
             *reinterpret_cast<real*>(qb + (r1.qoff >> sh) + lane * sizeof(real)) = q1;
         else if (NQ)
             *reinterpret_cast<real*>(qb + (2 * w + 1) * kTile * sizeof(real) + lane * sizeof(real)) = real(0);
+        if constexpr (NQ && WAVES != kWaves) load_nub();
         __syncthreads();
         if constexpr (NQ) {
             // A[cell][slot]: slot 4 kk + l/16, cell 16 cb + l%16 of the chunk buffer
 #pragma unroll
-            for (int kk = 0; kk < 4; ++kk) {
+            for (int kk = 0; kk < NKS; ++kk) {
                 const double a = reinterpret_cast<const double*>(
                     qb + (4 * kk + (lane >> 4)) * kTile * 8)[16 * nq_cb + (lane & 15)];
 #pragma unroll
-                for (int b = 0; b < 2; ++b)
-                    wacc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, nub[b][kk], wacc[b], 0, 0, 0);
+                for (int b = 0; b < NQB; ++b)
+                    if (WAVES == kWaves || nq_sb + b * (WAVES / 4) < nq_nsb)
+                        wacc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, nub[b][kk], wacc[b], 0, 0, 0);
             }
             continue;
         }
@@ -484,8 +498,8 @@ __global__ __launch_bounds__(WAVES * 64) void wdot_kernel(
     if constexpr (NQ) {
         // D: register i of lane l is cell 4 i + l/16, species l % 16 of the block
 #pragma unroll
-        for (int b = 0; b < 2; ++b) {
-            const int k = 16 * (nq_sb + 2 * b) + (lane & 15);
+        for (int b = 0; b < NQB; ++b) {
+            const int k = 16 * (nq_sb + b * (WAVES / 4)) + (lane & 15);
             if (k < m.S) {
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
@@ -528,11 +542,11 @@ template <typename real, int MAXPD, bool RKC, bool MM, bool NQ, bool LOG>
 hipError_t dispatch_own(const pyro_mech* m, int64_t n, int64_t ld, const real* r, const real* t,
                         const real* y, real* o, const double* params, hipStream_t stream,
                         const int64_t* nd) {
-    if constexpr (RKC && !NQ) {
+    if constexpr (RKC) {
         if (m->fw_waves != kWaves) {
-            if (m->max_own <= 8)
+            if (!NQ && m->max_own <= 8)
                 return launch_k<real, 2 * kWaves, 8, MAXPD, RKC, MM, false, LOG>(m, n, ld, r, t, y, o, params, stream, nd);
-            return launch_k<real, 2 * kWaves, 16, MAXPD, RKC, MM, false, LOG>(m, n, ld, r, t, y, o, params, stream, nd);
+            return launch_k<real, 2 * kWaves, 16, MAXPD, RKC, MM, NQ, LOG>(m, n, ld, r, t, y, o, params, stream, nd);
         }
     }
     if (m->max_own <= 8) return launch_k<real, kWaves, 8, MAXPD, RKC, MM, NQ, LOG>(m, n, ld, r, t, y, o, params, stream, nd);
@@ -545,13 +559,13 @@ hipError_t dispatch_own(const pyro_mech* m, int64_t n, int64_t ld, const real* r
 template <typename real, bool RKC, bool MM, bool NQ, bool LOG>
 hipError_t set_lds_variant(const pyro_mech* m, int bytes) {
     hipError_t e = hipSuccess;
-    if constexpr (RKC && !NQ) {
+    if constexpr (RKC) {
         if (m->fw_waves != kWaves) {
             const hipError_t big[] = {
-                set_lds<real, 2 * kWaves, 8, 8, RKC, MM, false, LOG>(bytes),
-                set_lds<real, 2 * kWaves, 16, 8, RKC, MM, false, LOG>(bytes),
-                MM ? hipSuccess : set_lds<real, 2 * kWaves, 8, 16, RKC, MM, false, LOG>(bytes),
-                MM ? hipSuccess : set_lds<real, 2 * kWaves, 16, 16, RKC, MM, false, LOG>(bytes)};
+                NQ ? hipSuccess : set_lds<real, 2 * kWaves, 8, 8, RKC, MM, false, LOG>(bytes),
+                set_lds<real, 2 * kWaves, 16, 8, RKC, MM, NQ, LOG>(bytes),
+                MM || NQ ? hipSuccess : set_lds<real, 2 * kWaves, 8, 16, RKC, MM, false, LOG>(bytes),
+                MM ? hipSuccess : set_lds<real, 2 * kWaves, 16, 16, RKC, MM, NQ, LOG>(bytes)};
             for (hipError_t x : big)
                 if (x != hipSuccess) e = x;
             return e;
@@ -633,7 +647,8 @@ hipError_t prepare_production_rates(const pyro_mech* m) {
 }
 
 bool nq_supported(const pyro_mech* m) {
-    return m->S <= 64 && m->max_own <= 16 && m->fw_waves == kWaves;
+    // blocks per wave: 2 with kWaves wavefronts, 3 with 2 kWaves
+    return m->max_own <= 16 && (m->fw_waves == kWaves ? m->S <= 64 : m->S <= 192);
 }
 
 hipError_t launch_production_rates(const pyro_mech* m, int64_t n, int64_t ld, int dtype,

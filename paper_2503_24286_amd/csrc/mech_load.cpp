@@ -617,13 +617,20 @@ int load_mechanism(const char* path, pyro_mech** out) {
         }
     }
 
-    // B fragments of the net coefficients per forward chunk (S <= 64)
-    const bool nq_table = S <= 64 && m->fw_waves == kWaves;
-    std::vector<double> nu_frag(nq_table ? size_t(std::max(n_chunks, 1)) * 4 * 4 * 64 : 1, 0.0);
+    // B fragments of the net coefficients per forward chunk,
+    // [chunk][species block][K-step][lane] = nu[16 sb + l%16][slot 4 kk + l/16]
+    // (S <= 64 with kWaves wavefronts, S <= 192 with 2 kWaves)
+    // (four blocks with kWaves wavefronts, zero beyond S: the kernel then
+    // multiplies every block without a test)
+    const int cslots = m->fw_waves * kRxnPerWave, nks = cslots / 4;
+    const int nsb = m->fw_waves == kWaves ? 4 : (S + 15) / 16;
+    const bool nq_table = m->fw_waves == kWaves ? S <= 64 : S <= 192;
+    std::vector<double> nu_frag(
+        nq_table ? size_t(std::max(n_chunks, 1)) * nsb * nks * 64 : 1, 0.0);
     if (nq_table)
         for (int c = 0; c < n_chunks; ++c)
-            for (int slot = 0; slot < kChunk; ++slot) {   // (only with kWaves waves)
-                const RxnRec& r = recs[size_t(c) * kChunk + slot];
+            for (int slot = 0; slot < cslots; ++slot) {
+                const RxnRec& r = recs[size_t(c) * cslots + slot];
                 if (r.cls == kNoReaction) continue;
                 const int j = r.prow;
                 std::vector<int> nu(S, 0);
@@ -633,7 +640,7 @@ int load_mechanism(const char* path, pyro_mech** out) {
                 for (int k = 0; k < S; ++k) {
                     if (!nu[k]) continue;
                     const int sb = k / 16, l = row * 16 + k % 16;
-                    nu_frag[((size_t(c) * 4 + sb) * 4 + kk) * 64 + l] = double(nu[k]);
+                    nu_frag[((size_t(c) * nsb + sb) * nks + kk) * 64 + l] = double(nu[k]);
                 }
             }
 
