@@ -407,16 +407,21 @@ def surrogate_leg(args, log):
         frac = int(count.item()) / n
         ms = _time_ms(lambda: model.eval(gm, rho, Td, Yd, thr_spread=ts, thr_resid=tr, out=out),
                       args.reps, stream)
+        # a threshold that admits no cell makes the call the exact kernel on
+        # every cell (the network is not run): no surrogate gain to report
+        admits = ts > 0 and tr > 0
         row = {"target": target, "thr_spread": ts, "thr_resid": tr,
                "fallback_fraction": round(frac, 5), "fallback_fraction_heldout": round(frac_cal, 5),
                "ms": round(ms, 4), "Mcells_s": round(n / ms / 1e3, 3),
-               "gain_vs_exact": round(ms_exact / ms, 4),
+               "gain_vs_exact": round(ms_exact / ms, 4) if admits else None,
+               "note": None if admits else "no admissible cell at this target: every cell "
+                                           "falls back, the network is not run, gain n/a",
                "err": {"p50": float(np.percentile(e, 50)), "p99": float(np.percentile(e, 99)),
                        "p99.9": float(np.percentile(e, 99.9)), "max": float(e.max()),
                        "frobenius": frob}}
         curve.append(row)
         log(f"surrogate: target {target}: fallback {frac:.4f}, {ms:.3f} ms, "
-            f"gain {ms_exact / ms:.3f}")
+            f"gain {ms_exact / ms:.3f}" + ("" if admits else " (no admissible cell)"))
     main_row = curve[0]
     gm.close()
     return {
