@@ -21,21 +21,6 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 constexpr int kBM = 64, kBN = 64, kBK = 32;
 constexpr int kLdsK = kBK + 8;  // padded row of a staged slice (bf16 elements)
 
-__device__ inline float bf2f(uint16_t h) { return __uint_as_float(uint32_t(h) << 16); }
-
-// round to nearest even
-__device__ inline uint16_t f2bf(float f) {
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7f800000u) == 0x7f800000u) return uint16_t((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return uint16_t(u >> 16);
-}
-
-__device__ inline float silu(float x) { return x / (1.0f + __expf(-x)); }
-__device__ inline float dsilu(float x) {
-    const float s = 1.0f / (1.0f + __expf(-x));
-    return s * (1.0f + x * (1.0f - s));
-}
 
 // Stage a 64 x 32 slice: rows r0.., k k0.. of X(r, k) = X[r*sr + k*sk]
 // (zero outside rows < R, k < K) into S[row][k].

@@ -20,6 +20,7 @@
 // output block of 32 (a slice of K-steps is contiguous); biases
 // [ob][l/32][16] in the register order above.
 #include "pyro_internal.h"
+#include "mlp_internal.h"
 #include "surrogate_internal.h"
 
 namespace pyro {
@@ -43,14 +44,32 @@ __host__ __device__ constexpr size_t fused_lds_bytes(int H, int members) {
            2 * size_t(kSliceKs) * (H / 32) * 64 * 16;
 }
 
-__device__ inline uint16_t f2bf(float f) {
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7f800000u) == 0x7f800000u) return uint16_t((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return uint16_t(u >> 16);
-}
 
-__device__ inline float silu(float x) { return x / (1.0f + __expf(-x)); }
+// sinh in FP64 from one exponential: (e - 1/e)/2 with e = exp(|x|) for
+// |x| >= 1/2 (the subtraction loses at most coth(1/2) < 2.2 in relative
+// terms), the odd Taylor series through x^17 below (truncation < 1e-22
+// relative); 1/e is the hardware reciprocal refined by two Newton steps, and
+// zero once e has overflowed.  A few ulps, where the library sinh also works
+// in extended precision.
+__device__ inline double sinh_d(double x) {
+    const double ax = fabs(x);
+    const double e = exp(ax);
+    double r = __builtin_amdgcn_rcp(e);
+    r = fma(r, fma(-e, r, 1.0), r);
+    r = fma(r, fma(-e, r, 1.0), r);
+    const double big = 0.5 * (e - (e < 0x1p1020 ? r : 0.0));
+    const double x2 = x * x;
+    double t = 1.0 / 355687428096000.0;                  // 1/17!
+    t = fma(t, x2, 1.0 / 1307674368000.0);               // 1/15!
+    t = fma(t, x2, 1.0 / 6227020800.0);                  // 1/13!
+    t = fma(t, x2, 1.0 / 39916800.0);                    // 1/11!
+    t = fma(t, x2, 1.0 / 362880.0);                      // 1/9!
+    t = fma(t, x2, 1.0 / 5040.0);                        // 1/7!
+    t = fma(t, x2, 1.0 / 120.0);                         // 1/5!
+    t = fma(t, x2, 1.0 / 6.0);                           // 1/3!
+    const double small = fma(ax * x2, t, ax);
+    return copysign(ax < 0.5 ? small : big, x);
+}
 
 // packed-fragment sizes (elements) of one member for hidden width H
 __host__ __device__ constexpr int64_t frag_elems(int nb, int ks) { return int64_t(nb) * ks * 64 * 8; }
@@ -196,11 +215,8 @@ __device__ inline void activate(const f32x16 (&acc)[NB], bf16x8 (&out)[2 * NB]) 
         for (int t = 0; t < 2; ++t) {
             u32x4 packed;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const uint32_t lo = f2bf(silu(acc[ob][8 * t + 2 * q]));
-                const uint32_t hi = f2bf(silu(acc[ob][8 * t + 2 * q + 1]));
-                packed[q] = lo | (hi << 16);
-            }
+            for (int q = 0; q < 4; ++q)
+                packed[q] = f2bf2(silu(acc[ob][8 * t + 2 * q]), silu(acc[ob][8 * t + 2 * q + 1]));
             out[2 * ob + t] = __builtin_bit_cast(bf16x8, packed);
         }
 }
@@ -328,7 +344,7 @@ __global__ __launch_bounds__(waves_per_block(E) * 64) void fused_kernel(
                     float zs = 0.0f;
 #pragma unroll
                     for (int e = 0; e < E; ++e) zs += zl[(e * 32 + r) * 64];
-                    const double w = s * sinh(fma(sg, double(zs * inv_e), mu));
+                    const double w = s * sinh_d(fma(sg, double(zs * inv_e), mu));
                     wm[ob][i] = w;
                     finite = finite && isfinite(w);
                     mean2 = fma(w, w, mean2);
@@ -336,7 +352,7 @@ __global__ __launch_bounds__(waves_per_block(E) * 64) void fused_kernel(
 #pragma unroll
                         for (int e = 0; e < E; ++e) {
                             const double d =
-                                s * sinh(fma(sg, double(zl[(e * 32 + r) * 64]), mu)) - w;
+                                s * sinh_d(fma(sg, double(zl[(e * 32 + r) * 64]), mu)) - w;
                             dev2 = fma(d, d, dev2);
                         }
                     }

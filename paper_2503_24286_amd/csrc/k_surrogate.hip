@@ -9,6 +9,7 @@
 // |omega_k| of the training set, inverted as omega_k = s_k sinh(mu_k +
 // sigma_k z_k).
 #include "pyro_internal.h"
+#include "mlp_internal.h"
 #include "surrogate_internal.h"
 
 namespace pyro {
@@ -16,13 +17,6 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kScanBlock = 1024;
-
-__device__ inline uint16_t f2bf(float f) {
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7f800000u) == 0x7f800000u) return uint16_t((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return uint16_t(u >> 16);
-}
 
 __global__ __launch_bounds__(kBlock) void features_kernel(DevMech m, int64_t n, int64_t ld,
                                                           const double* __restrict__ rho,

@@ -408,6 +408,54 @@ def test_eval_mixed_thresholds_route_cells_by_their_indicators(env):
     assert np.array_equal(got[:, ~f].view(np.uint64), w_inf[:, ~f].view(np.uint64))
 
 
+def test_eval_full_size_routing_and_outputs(env):
+    """2^22 cells (the evaluation workload) in one call, on the device: every
+    cell routed by its own indicators, fallen-back cells bitwise equal to the
+    exact kernel, kept cells bitwise equal to the no-fallback prediction, the
+    count equal to the flags' sum; and sampled cells' member outputs against
+    the oracle's BF16 network (multi-block grid, compaction over millions of
+    flags)."""
+    torch, pyro, _lib, sur, gms = env
+    m = mechs.load_config(1)
+    gm = gms[1]
+    model = _trained_like_surrogate(sur, m)
+    n = 1 << 22
+    from pyro_synth.states import draw_states
+    from oracle import eos
+    T, p, Y = draw_states(4, n, m.S)
+    announce(f"surrogate eval full size n={n}")
+    t, pd, y = to_dev(torch, T, p, Y)
+    r = pyro.density(gm, pd, t, y)
+    del pd
+    w_inf, _, _, ind = model.eval(gm, r, t, y, indicators=True)
+    ts = float(torch.quantile(ind[0, ::64], 0.5))
+    tr = float(torch.quantile(ind[1, ::64], 0.6))
+    w, flags, count, _ = model.eval(gm, r, t, y, thr_spread=ts, thr_resid=tr)
+    exact = pyro.production_rates(gm, r, t, y)
+    f = flags.bool()
+    expect = ~((ind[0] < ts) & (ind[1] < tr) & torch.isfinite(w_inf).all(dim=0))
+    assert bool((f == expect).all())
+    nf = int(f.sum())
+    assert int(count.item()) == nf and 0 < nf < n
+    same = lambda a, b: bool((a.view(torch.int64) == b.view(torch.int64)).all())  # noqa: E731
+    assert same(w[:, f], exact[:, f]) and same(w[:, ~f], w_inf[:, ~f])
+    idx = np.array([0, 1, 31, 32, 999_983, n // 2, n - 33, n - 1])
+    Zs = model.outputs(gm, r[idx], t[idx], y[:, idx].contiguous()).cpu().numpy()
+    torch.cuda.synchronize()
+    rho = eos.density(m, p[idx], T[idx], Y[:, idx])
+    nrm = model.norm
+    X = ref.bf16_round(ref.features(m, rho, T[idx], Y[:, idx], nrm.feat_shift.astype(np.float64),
+                                    nrm.feat_scale.astype(np.float64)))
+    Zfull = model.outputs(gm, r, t, y)[:, torch.from_numpy(idx).cuda()].cpu().numpy()
+    assert np.array_equal(Zfull, Zs)        # the full launch computes the same cells
+    for e in range(model.members):
+        Ws, bs = ref.unpack(256, ref.from_bf16_bits(model.weights[e]),
+                            model.biases[e].astype(np.float64))
+        _, Hh, Zr = ref.forward(X, Ws, bs)
+        scale = np.abs(Hh[2]) @ np.abs(Ws[3]) + np.abs(bs[3])
+        assert np.all(np.abs(Zs[e] - Zr) <= 4 * BF16_STEP * scale + 1e-6)
+
+
 def test_eval_rejects_bad_arguments(env):
     torch, pyro, _lib, sur, gms = env
     m = mechs.load_config(1)
@@ -440,3 +488,17 @@ def test_training_reduces_the_loss(env):
     assert hist[-1] < 0.5 * hist[0]
     # normalised targets have unit variance: the network must beat the mean
     assert hist[-1] < 0.5
+
+
+@pytest.mark.skip(reason="no gain exists to assert: with 2^24 training states the held-out "
+                         "per-cell error without fallback has median 0.36, so at the 1e-3 and "
+                         "1e-2 targets the calibrated thresholds admit no cell (every cell falls "
+                         "back and the call is the exact kernel); BF16 activations alone put the "
+                         "error of this representation above 1e-3 (the measured floor is in the "
+                         "design notes)")
+def test_surrogate_beats_the_exact_kernel_at_1e3(env):
+    """What the trained network gains over the method without it: at the
+    1e-3 target (per-cell normwise error after fallback, p99.9), fewer than
+    half of the cells fall back and surrogate + fallback is faster than the
+    exact kernel alone on 2^22 cells."""
+    raise AssertionError("enable once a configuration reaches the target")
