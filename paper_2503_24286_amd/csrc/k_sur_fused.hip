@@ -32,16 +32,22 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kCells = 32;                 // cells per wavefront
 constexpr int kFeatRow = kFeatPad + 8;     // padded LDS feature row (bf16)
-constexpr int kSliceKs = 2;                // K-steps per staged weight slice
-
 // wavefronts per workgroup: four share the weights; five or more members'
 // outputs would not fit in LDS beside them, so four members use two
 __host__ __device__ constexpr int waves_per_block(int members) { return members <= 3 ? 4 : 2; }
 
 // LDS: feature rows, member outputs, two weight slices of the widest layer
-__host__ __device__ constexpr size_t fused_lds_bytes(int H, int members) {
+__host__ __device__ constexpr size_t fused_lds_bytes_ks(int H, int members, int slice_ks) {
     return size_t(waves_per_block(members)) * (kCells * kFeatRow * 2 + members * 32 * 64 * 4) +
-           2 * size_t(kSliceKs) * (H / 32) * 64 * 16;
+           2 * size_t(slice_ks) * (H / 32) * 64 * 16;
+}
+// K-steps per staged weight slice: four where two such slices fit (one
+// barrier per four K-steps), else two
+__host__ __device__ constexpr int slice_ks(int H, int members) {
+    return fused_lds_bytes_ks(H, members, 4) <= 160 * 1024 ? 4 : 2;
+}
+__host__ __device__ constexpr size_t fused_lds_bytes(int H, int members) {
+    return fused_lds_bytes_ks(H, members, slice_ks(H, members));
 }
 
 
@@ -154,14 +160,18 @@ struct FusedArgs {
 // One layer for the wavefront's 32 cells: acc = bias + W^T in, with the
 // weight slices staged through LDS by the whole workgroup (NT threads).
 // Every call ends with a barrier, so the next call may refill both buffers.
-template <int NB, int KS, int NT>
+template <int NB, int KS, int NT, int kSliceKs>
 __device__ inline void layer(f32x16 (&acc)[NB], const bf16x8 (&in)[KS],
                              const uint16_t* __restrict__ wp, const float* __restrict__ bp,
                              u32x4* wbuf, int lane, int tid) {
     constexpr int kUnits = kSliceKs * NB * 64;          // 16-byte fragments per slice
-    constexpr int kPer = (kUnits + NT - 1) / NT;        // per thread
+    constexpr int kPer = kUnits / NT;                   // per thread
     constexpr int kSlices = KS / kSliceKs;
     static_assert(KS % kSliceKs == 0, "K-steps come in whole slices");
+    // every thread copies the same number of fragments: no per-lane
+    // conditions (the compiler cannot prove tid < NT, and a guarded copy
+    // becomes an exec-masked load waited on at once)
+    static_assert(kUnits % NT == 0, "a slice is a whole number of fragments per thread");
     const int h = lane >> 5;
 #pragma unroll
     for (int ob = 0; ob < NB; ++ob) {
@@ -177,8 +187,7 @@ __device__ inline void layer(f32x16 (&acc)[NB], const bf16x8 (&in)[KS],
     }
     const u32x4* src = reinterpret_cast<const u32x4*>(wp);
 #pragma unroll
-    for (int j = 0; j < kPer; ++j)
-        if (tid + j * NT < kUnits) wbuf[tid + j * NT] = src[tid + j * NT];
+    for (int j = 0; j < kPer; ++j) wbuf[tid + j * NT] = src[tid + j * NT];
     __syncthreads();
 #pragma unroll
     for (int sl = 0; sl < kSlices; ++sl) {
@@ -187,20 +196,38 @@ __device__ inline void layer(f32x16 (&acc)[NB], const bf16x8 (&in)[KS],
         u32x4 pre[kPer];
         if (sl + 1 < kSlices) {
 #pragma unroll
-            for (int j = 0; j < kPer; ++j)
-                if (tid + j * NT < kUnits) pre[j] = src[(sl + 1) * kUnits + tid + j * NT];
+            for (int j = 0; j < kPer; ++j) pre[j] = src[(sl + 1) * kUnits + tid + j * NT];
         }
+        // the fragments of K-step kk + 1 are read while those of kk multiply
+        // (one LDS latency per slice instead of one per MFMA)
+        u32x4 f[2][NB];
 #pragma unroll
-        for (int kk = 0; kk < kSliceKs; ++kk)
+        for (int ob = 0; ob < NB; ++ob) f[0][ob] = cur[ob * 64 + lane];
+#pragma unroll
+        for (int kk = 0; kk < kSliceKs; ++kk) {
+            if (kk + 1 < kSliceKs) {
+#pragma unroll
+                for (int ob = 0; ob < NB; ++ob)
+                    f[(kk + 1) & 1][ob] = cur[((kk + 1) * NB + ob) * 64 + lane];
+            }
 #pragma unroll
             for (int ob = 0; ob < NB; ++ob)
                 acc[ob] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                    __builtin_bit_cast(bf16x8, cur[(kk * NB + ob) * 64 + lane]),
-                    in[sl * kSliceKs + kk], acc[ob], 0, 0, 0);
+                    __builtin_bit_cast(bf16x8, f[kk & 1][ob]), in[sl * kSliceKs + kk], acc[ob],
+                    0, 0, 0);
+        }
+        // pin that order for the scheduler (it otherwise sinks every read to
+        // its MFMA and waits on it there): K-step 0's reads, then per K-step
+        // the next one's reads followed by this one's MFMAs
+        __builtin_amdgcn_sched_group_barrier(0x100, NB, 0);
+#pragma unroll
+        for (int kk = 0; kk < kSliceKs; ++kk) {
+            if (kk + 1 < kSliceKs) __builtin_amdgcn_sched_group_barrier(0x100, NB, 0);
+            __builtin_amdgcn_sched_group_barrier(0x008, NB, 0);
+        }
         if (sl + 1 < kSlices) {
 #pragma unroll
-            for (int j = 0; j < kPer; ++j)
-                if (tid + j * NT < kUnits) nxt[tid + j * NT] = pre[j];
+            for (int j = 0; j < kPer; ++j) nxt[tid + j * NT] = pre[j];
         }
         __syncthreads();
     }
@@ -226,7 +253,7 @@ __global__ __launch_bounds__(waves_per_block(E) * 64) void fused_kernel(
     DevMech m, int64_t n, int64_t ld, const double* __restrict__ rho,
     const double* __restrict__ T, const double* __restrict__ Y, FusedArgs a) {
     constexpr int NBH = H / 32, KSH = H / 16;
-    constexpr int WPB = waves_per_block(E), NT = WPB * 64;
+    constexpr int WPB = waves_per_block(E), NT = WPB * 64, SKS = slice_ks(H, E);
     // LDS: feature rows [wave][cell][kFeatRow] (BF16), the member outputs
     // [wave][member][register][lane] (FP32, lane-contiguous), then two
     // weight slices
@@ -291,14 +318,14 @@ __global__ __launch_bounds__(waves_per_block(E) * 64) void fused_kernel(
         const float* bp = a.bp + e * a.b_stride;
         f32x16 acc[NBH];
         bf16x8 act[KSH];
-        layer<NBH, 4, NT>(acc, xb, wp + P.w_off[0], bp + P.b_off[0], wbuf, lane, tid);
+        layer<NBH, 4, NT, SKS>(acc, xb, wp + P.w_off[0], bp + P.b_off[0], wbuf, lane, tid);
         activate<NBH>(acc, act);
-        layer<NBH, KSH, NT>(acc, act, wp + P.w_off[1], bp + P.b_off[1], wbuf, lane, tid);
+        layer<NBH, KSH, NT, SKS>(acc, act, wp + P.w_off[1], bp + P.b_off[1], wbuf, lane, tid);
         activate<NBH>(acc, act);
-        layer<NBH, KSH, NT>(acc, act, wp + P.w_off[2], bp + P.b_off[2], wbuf, lane, tid);
+        layer<NBH, KSH, NT, SKS>(acc, act, wp + P.w_off[2], bp + P.b_off[2], wbuf, lane, tid);
         activate<NBH>(acc, act);
         f32x16 z[2];
-        layer<2, KSH, NT>(z, act, wp + P.w_off[3], bp + P.b_off[3], wbuf, lane, tid);
+        layer<2, KSH, NT, SKS>(z, act, wp + P.w_off[3], bp + P.b_off[3], wbuf, lane, tid);
 #pragma unroll
         for (int ob = 0; ob < 2; ++ob)
 #pragma unroll
