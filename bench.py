@@ -394,7 +394,12 @@ def surrogate_leg(args, log):
     out = torch.empty_like(w_ex)
     ms_exact = _time_ms(lambda: pyro.production_rates(gm, rho, Td, Yd, out=out), args.reps,
                         stream)
-    ms_mlp = _time_ms(lambda: model.eval(gm, rho, Td, Yd, out=out), args.reps, stream)
+    # the surrogate without fallback (thresholds infinite: network, inverse
+    # transform, indicators, no exact cell) and the network's member outputs
+    # alone (features and the four layers of every member)
+    ms_mlp = _time_ms(lambda: model.eval(gm, rho, Td, Yd, thr_spread=math.inf,
+                                         thr_resid=math.inf, out=out), args.reps, stream)
+    ms_net = _time_ms(lambda: model.outputs(gm, rho, Td, Yd), args.reps, stream)
     ref_norm = torch.sqrt((w_ex * w_ex).sum(0))
     r2_sum = float((ref_norm.double() ** 2).sum())
     curve = []
@@ -424,6 +429,7 @@ def surrogate_leg(args, log):
             f"gain {ms_exact / ms:.3f}" + ("" if admits else " (no admissible cell)"))
     main_row = curve[0]
     gm.close()
+    net_flops = 2 * args.members * sum(a * b for a, b in sur.layer_dims(args.hidden))
     return {
         "workload": f"53-species mechanism; ensemble of {args.members} MLPs 64(56 used)-"
                     f"{args.hidden}-{args.hidden}-{args.hidden}-64(53 used), SiLU, BF16 "
@@ -435,6 +441,11 @@ def surrogate_leg(args, log):
         "heldout_err_without_fallback": held_out,
         "exact_ms": round(ms_exact, 4), "exact_Mcells_s": round(n / ms_exact / 1e3, 3),
         "mlp_only_ms": round(ms_mlp, 4), "mlp_only_Mcells_s": round(n / ms_mlp / 1e3, 3),
+        "network_outputs_ms": round(ms_net, 4),
+        "network_roofline": {"bound": "mfma", "unit": "TFLOP/s", "peak": 2500.0,
+                             "achieved": round(net_flops * n / (ms_net * 1e-3) / 1e12, 1),
+                             "frac": round(net_flops * n / (ms_net * 1e-3) / 2.5e15, 4),
+                             "flops_per_cell": net_flops},
         "at_1e-3": main_row, "curve": curve,
     }
 

@@ -317,7 +317,7 @@ int pyro_surrogate_outputs(const pyro_mech* m, const pyro_surrogate* sur, int64_
         e = launch_fused(m, sur->hidden, sur->n_members, n, ld, rho, T, Y, p.wp, p.bp, p.w_stride,
                          p.b_stride, sur->feat_shift, sur->feat_scale, sur->target_scale,
                          sur->target_mean, sur->target_std, 0.0, 0.0, nullptr, nullptr, nullptr, Z,
-                         s);
+                         nullptr, s);
     return e == hipSuccess ? PYRO_OK : hip_fail(e, "surrogate output launch");
 }
 
@@ -362,13 +362,17 @@ int pyro_surrogate_eval(const pyro_mech* m, const pyro_surrogate* sur, int64_t n
     double* yc = reinterpret_cast<double*>(take(size_t(n) * m->S * 8 * 2));
     double* wc = yc + size_t(n) * m->S;
 
-    // prediction, indicators and flags in one pass; then the flagged cells,
-    // compacted in ascending order, through the exact kernel
+    // the network (member outputs staged in the compacted-state region, free
+    // until the compaction), then prediction, indicators and flags; then the
+    // flagged cells, compacted in ascending order, through the exact kernel.
+    // The staged outputs, members x S x n floats, fit that region (2 S n
+    // doubles) for up to four members.
+    static_assert(kMaxMembers <= 4, "staged member outputs must fit the compacted-state region");
     if (e == hipSuccess)
         e = launch_fused(m, sur->hidden, sur->n_members, n, ld, rho, T, Y, p.wp, p.bp, p.w_stride,
                          p.b_stride, sur->feat_shift, sur->feat_scale, sur->target_scale,
                          sur->target_mean, sur->target_std, thr_spread, thr_resid, wdot,
-                         fell_back, indicators, nullptr, s);
+                         fell_back, indicators, nullptr, reinterpret_cast<float*>(yc), s);
     if (e == hipSuccess) e = launch_compaction(n, fell_back, counts, n_fallback, idx, s);
     if (e == hipSuccess) e = launch_gather(m->S, n, ld, n_fallback, idx, rho, T, Y, rc, tc, yc, s);
     if (e == hipSuccess)

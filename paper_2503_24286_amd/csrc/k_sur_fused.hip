@@ -1,6 +1,11 @@
-// Fused surrogate inference: features, every ensemble member's four layers,
-// the ensemble mean, the inverse target transform and the error indicators,
-// in one pass over the cells.  Activations never leave registers.
+// Surrogate inference in two kernels.  The network kernel forms the features
+// and runs every ensemble member's four layers; activations never leave
+// registers and each member's outputs go straight from registers to global
+// memory (species-major for the evaluation, cell-major for the raw-output
+// call).  The post kernel, one thread per cell at full occupancy, forms the
+// ensemble mean, the inverse target transform and the error indicators in
+// FP64 (they ran at the network's one wavefront per SIMD when fused, where
+// their latencies had nothing to hide behind).
 //
 // One wavefront owns 32 cells.  Each layer is computed transposed,
 // out^T [N x 32 cells] = W^T [N x K] in^T [K x 32 cells], with
@@ -32,24 +37,23 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kCells = 32;                 // cells per wavefront
 constexpr int kFeatRow = kFeatPad + 8;     // padded LDS feature row (bf16)
-// wavefronts per workgroup: four share the weights; five or more members'
-// outputs would not fit in LDS beside them, so four members use two
-__host__ __device__ constexpr int waves_per_block(int members) { return members <= 3 ? 4 : 2; }
+// wavefronts per workgroup (they share the weights)
+__host__ __device__ constexpr int waves_per_block(int) { return 4; }
 
-// LDS: feature rows, member outputs, two weight slices of the widest layer
+// LDS: feature rows, two weight slices of the widest layer
 __host__ __device__ constexpr size_t fused_lds_bytes_ks(int H, int members, int slice_ks) {
-    return size_t(waves_per_block(members)) * (kCells * kFeatRow * 2 + members * 32 * 64 * 4) +
+    return size_t(waves_per_block(members)) * kCells * kFeatRow * 2 +
            2 * size_t(slice_ks) * (H / 32) * 64 * 16;
 }
-// K-steps per staged weight slice: four where two such slices fit (one
-// barrier per four K-steps), else two
+// K-steps per staged weight slice: as many as let two slices fit (one
+// barrier per slice)
 __host__ __device__ constexpr int slice_ks(int H, int members) {
-    return fused_lds_bytes_ks(H, members, 4) <= 160 * 1024 ? 4 : 2;
+    return fused_lds_bytes_ks(H, members, 8) <= 160 * 1024 ? 8
+         : fused_lds_bytes_ks(H, members, 4) <= 160 * 1024 ? 4 : 2;
 }
 __host__ __device__ constexpr size_t fused_lds_bytes(int H, int members) {
     return fused_lds_bytes_ks(H, members, slice_ks(H, members));
 }
-
 
 // sinh in FP64 from one exponential: (e - 1/e)/2 with e = exp(|x|) for
 // |x| >= 1/2 (the subtraction loses at most coth(1/2) < 2.2 in relative
@@ -147,23 +151,17 @@ struct FusedArgs {
     int64_t w_stride, b_stride;
     const float* shift;
     const float* scale;
-    const double* ts;
-    const double* tmu;
-    const double* tsig;
-    double thr_spread, thr_resid;
-    double* wdot;          // eval: [S][ld]
-    uint8_t* flag;         // eval: [n]
-    double* ind;           // eval, optional: spread [n], residual [n]
-    float* zout;           // raw mode: [members][n][64]
+    float* zout;           // raw mode: [members][n][64]; else [members][S][n]
 };
 
 // One layer for the wavefront's 32 cells: acc = bias + W^T in, with the
 // weight slices staged through LDS by the whole workgroup (NT threads).
 // Every call ends with a barrier, so the next call may refill both buffers.
-template <int NB, int KS, int NT, int kSliceKs>
+template <int NB, int KS, int NT, int SKS>
 __device__ inline void layer(f32x16 (&acc)[NB], const bf16x8 (&in)[KS],
                              const uint16_t* __restrict__ wp, const float* __restrict__ bp,
                              u32x4* wbuf, int lane, int tid) {
+    constexpr int kSliceKs = SKS < KS ? SKS : KS;       // a slice never spans layers
     constexpr int kUnits = kSliceKs * NB * 64;          // 16-byte fragments per slice
     constexpr int kPer = kUnits / NT;                   // per thread
     constexpr int kSlices = KS / kSliceKs;
@@ -254,17 +252,14 @@ __global__ __launch_bounds__(waves_per_block(E) * 64) void fused_kernel(
     const double* __restrict__ T, const double* __restrict__ Y, FusedArgs a) {
     constexpr int NBH = H / 32, KSH = H / 16;
     constexpr int WPB = waves_per_block(E), NT = WPB * 64, SKS = slice_ks(H, E);
-    // LDS: feature rows [wave][cell][kFeatRow] (BF16), the member outputs
-    // [wave][member][register][lane] (FP32, lane-contiguous), then two
-    // weight slices
+    // LDS: feature rows [wave][cell][kFeatRow] (BF16), then two weight
+    // slices
     extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wv = tid >> 6;
     uint16_t* feat = reinterpret_cast<uint16_t*>(lds) + wv * kCells * kFeatRow;
-    unsigned char* zbase = lds + WPB * kCells * kFeatRow * 2;
-    float* zl = reinterpret_cast<float*>(zbase) + wv * E * 32 * 64 + lane;
-    u32x4* wbuf = reinterpret_cast<u32x4*>(zbase + WPB * E * 32 * 64 * 4);
+    u32x4* wbuf = reinterpret_cast<u32x4*>(lds + WPB * kCells * kFeatRow * 2);
     // every wavefront takes part in the weight staging and its barriers;
     // cells past n compute on cell n - 1 and write nothing
     const int64_t c0 = (int64_t(blockIdx.x) * WPB + wv) * kCells;
@@ -310,7 +305,7 @@ __global__ __launch_bounds__(waves_per_block(E) * 64) void fused_kernel(
     for (int s = 0; s < 4; ++s) xb[s] = *reinterpret_cast<const bf16x8*>(fr + 16 * s + 8 * h);
 
     // ---- ensemble members (the loop stays rolled: one member's code is
-    // already 320 MFMAs, and its outputs go to LDS)
+    // already 320 MFMAs)
 #pragma nounroll
     for (int e = 0; e < E; ++e) {
         const PackLayout P(H);
@@ -326,99 +321,91 @@ __global__ __launch_bounds__(waves_per_block(E) * 64) void fused_kernel(
         activate<NBH>(acc, act);
         f32x16 z[2];
         layer<2, KSH, NT, SKS>(z, act, wp + P.w_off[3], bp + P.b_off[3], wbuf, lane, tid);
-#pragma unroll
-        for (int ob = 0; ob < 2; ++ob)
-#pragma unroll
-            for (int i = 0; i < 16; ++i) zl[(e * 32 + ob * 16 + i) * 64] = z[ob][i];
-    }
-    // outputs are read back by the lane that wrote them: no wave exchange
-
-    if constexpr (RAW) {
+        // register i of block ob holds output k = output_index(ob, h, i):
+        // species-major stores are two 128-byte runs of cells per register
         if (valid) {
-            for (int e = 0; e < E; ++e)
-#pragma unroll
-                for (int ob = 0; ob < 2; ++ob)
-#pragma unroll
-                    for (int i = 0; i < 16; ++i)
-                        a.zout[(int64_t(e) * n + cell) * kOutPad + output_index(ob, h, i)] =
-                            zl[(e * 32 + ob * 16 + i) * 64];
-        }
-        return;
-    } else {
-        // ---- ensemble mean, inverse transform, indicators (this lane's 32
-        // outputs; per-cell sums completed with the other lane half)
-        const float inv_e = 1.0f / float(E);
-        double wm[2][16];
-        double mean2 = 0.0, dev2 = 0.0;
-        bool finite = true;
-        // a lane's species is k0 (half 0) or k0 + 4 (half 1): both table
-        // entries come from scalar loads and the lane selects its own
-        const cptr<double> ts = cst(a.ts), tmu = cst(a.tmu), tsig = cst(a.tsig);
-#pragma unroll
-        for (int ob = 0; ob < 2; ++ob)
-#pragma unroll
-            for (int i = 0; i < 16; ++i) {
-                const int k0 = output_index(ob, 0, i);
-                const int k = k0 + 4 * h;
-                const int r = ob * 16 + i;
-                wm[ob][i] = 0.0;
-                if (k0 >= m.S) continue;
-                const bool has1 = k0 + 4 < m.S;
-                const double s = h ? (has1 ? ts[k0 + 4] : 1.0) : ts[k0];
-                const double mu = h ? (has1 ? tmu[k0 + 4] : 0.0) : tmu[k0];
-                const double sg = h ? (has1 ? tsig[k0 + 4] : 0.0) : tsig[k0];
-                if (k < m.S) {
-                    float zs = 0.0f;
-#pragma unroll
-                    for (int e = 0; e < E; ++e) zs += zl[(e * 32 + r) * 64];
-                    const double w = s * sinh_d(fma(sg, double(zs * inv_e), mu));
-                    wm[ob][i] = w;
-                    finite = finite && isfinite(w);
-                    mean2 = fma(w, w, mean2);
-                    if (E > 1) {
-#pragma unroll
-                        for (int e = 0; e < E; ++e) {
-                            const double d =
-                                s * sinh_d(fma(sg, double(zl[(e * 32 + r) * 64]), mu)) - w;
-                            dev2 = fma(d, d, dev2);
-                        }
-                    }
-                    if (valid) a.wdot[size_t(k) * ld + cell] = w;
-                }
-            }
-        // element residual ||A w|| / || |A| |w| ||
-        double r2 = 0.0, q2 = 0.0;
-        for (int el = 0; el < m.E; ++el) {
-            const cptr<double> ce = cst(m.comp) + size_t(el) * m.S;
-            double r = 0.0, q = 0.0;
 #pragma unroll
             for (int ob = 0; ob < 2; ++ob)
 #pragma unroll
                 for (int i = 0; i < 16; ++i) {
-                    const int k0 = output_index(ob, 0, i);
-                    if (k0 >= m.S) continue;
-                    // wm is zero for a lane whose species is past S
-                    const double ak = h ? (k0 + 4 < m.S ? ce[k0 + 4] : 0.0) : ce[k0];
-                    r = fma(ak, wm[ob][i], r);
-                    q = fma(fabs(ak), fabs(wm[ob][i]), q);
+                    const int k = output_index(ob, h, i);
+                    if constexpr (RAW) {
+                        a.zout[(int64_t(e) * n + cell) * kOutPad + k] = z[ob][i];
+                    } else if (k < m.S) {
+                        a.zout[(int64_t(e) * m.S + k) * n + cell] = z[ob][i];
+                    }
                 }
-            r += __shfl_xor(r, 32);
-            q += __shfl_xor(q, 32);
-            r2 = fma(r, r, r2);
-            q2 = fma(q, q, q2);
         }
-        mean2 += __shfl_xor(mean2, 32);
-        dev2 += __shfl_xor(dev2, 32);
-        const int fin = __shfl_xor(int(finite), 32) & int(finite);
-        if (h == 0 && valid) {
-            const double spread = sqrt(dev2 / E) / fmax(sqrt(mean2), 1e-300);
-            const double resid = q2 > 0.0 ? sqrt(r2 / q2) : 0.0;
-            a.flag[cell] = (fin && spread < a.thr_spread && resid < a.thr_resid) ? 0 : 1;
-            if (a.ind) {
-                a.ind[cell] = spread;
-                a.ind[n + cell] = resid;
+    }
+}
+
+// Ensemble mean, inverse target transform and indicators of one cell per
+// thread from the staged member outputs z [E][S][n]: omega_k = s_k
+// sinh(sigma_k zbar_k + mu_k) with zbar the FP32 mean of the members;
+// spread = sqrt(sum_e sum_k (omega_ek - omega_k)^2 / E) / ||omega||;
+// residual = ||A omega|| / || |A| |omega| ||; flag = 0 only where all are
+// finite and both indicators are under their thresholds.
+template <int E>
+__global__ __launch_bounds__(256) void post_kernel(DevMech m, int64_t n, int64_t ld,
+                                                   const float* __restrict__ z,
+                                                   const double* __restrict__ ts,
+                                                   const double* __restrict__ tmu,
+                                                   const double* __restrict__ tsig,
+                                                   double thr_spread, double thr_resid,
+                                                   double* __restrict__ wdot,
+                                                   uint8_t* __restrict__ flag,
+                                                   double* __restrict__ ind) {
+    const int64_t cell = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (cell >= n) return;
+    const float inv_e = 1.0f / float(E);
+    const cptr<double> cs = cst(ts), cm = cst(tmu), cg = cst(tsig);
+    double r[kMaxElements], q[kMaxElements];
+#pragma unroll
+    for (int el = 0; el < kMaxElements; ++el) r[el] = q[el] = 0.0;
+    double mean2 = 0.0, dev2 = 0.0;
+    bool finite = true;
+    for (int k = 0; k < m.S; ++k) {
+        float ze[E];
+        float zs = 0.0f;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            ze[e] = z[(int64_t(e) * m.S + k) * n + cell];
+            zs += ze[e];
+        }
+        const double s = cs[k], mu = cm[k], sg = cg[k];
+        const double w = s * sinh_d(fma(sg, double(zs * inv_e), mu));
+        finite = finite && isfinite(w);
+        mean2 = fma(w, w, mean2);
+        if (E > 1) {
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const double d = s * sinh_d(fma(sg, double(ze[e]), mu)) - w;
+                dev2 = fma(d, d, dev2);
             }
         }
+        wdot[size_t(k) * ld + cell] = w;
+        const cptr<double> ce = cst(m.comp) + k;
+#pragma unroll
+        for (int el = 0; el < kMaxElements; ++el)
+            if (el < m.E) {
+                const double ak = ce[size_t(el) * m.S];
+                r[el] = fma(ak, w, r[el]);
+                q[el] = fma(fabs(ak), fabs(w), q[el]);
+            }
+    }
+    double r2 = 0.0, q2 = 0.0;
+#pragma unroll
+    for (int el = 0; el < kMaxElements; ++el)
+        if (el < m.E) {
+            r2 = fma(r[el], r[el], r2);
+            q2 = fma(q[el], q[el], q2);
+        }
+    const double spread = sqrt(dev2 / E) / fmax(sqrt(mean2), 1e-300);
+    const double resid = q2 > 0.0 ? sqrt(r2 / q2) : 0.0;
+    flag[cell] = (finite && spread < thr_spread && resid < thr_resid) ? 0 : 1;
+    if (ind) {
+        ind[cell] = spread;
+        ind[n + cell] = resid;
     }
 }
 
@@ -440,6 +427,16 @@ hipError_t launch_fused_he(const pyro_mech* m, int64_t n, int64_t ld, const doub
     else
         hipLaunchKernelGGL((fused_kernel<H, E, false>), grid, dim3(WPB * 64), lds,
                            stream, m->dev, n, ld, rho, T, Y, a);
+    return hipGetLastError();
+}
+
+template <int E>
+hipError_t launch_post_e(const pyro_mech* m, int64_t n, int64_t ld, const float* z,
+                         const double* ts, const double* tmu, const double* tsig,
+                         double thr_spread, double thr_resid, double* wdot, uint8_t* flag,
+                         double* ind, hipStream_t stream) {
+    hipLaunchKernelGGL(post_kernel<E>, dim3(unsigned((n + 255) / 256)), dim3(256), 0, stream,
+                       m->dev, n, ld, z, ts, tmu, tsig, thr_spread, thr_resid, wdot, flag, ind);
     return hipGetLastError();
 }
 
@@ -479,14 +476,21 @@ hipError_t launch_fused(const pyro_mech* m, int hidden, int members, int64_t n, 
                         const float* shift, const float* scale, const double* ts,
                         const double* tmu, const double* tsig, double thr_spread,
                         double thr_resid, double* wdot, uint8_t* flag, double* ind, float* zout,
-                        hipStream_t stream) {
-    FusedArgs a{wp, bp, w_stride, b_stride, shift, scale, ts, tmu, tsig, thr_spread,
-                thr_resid, wdot, flag, ind, zout};
+                        float* zstage, hipStream_t stream) {
     const bool raw = zout != nullptr;
+    FusedArgs a{wp, bp, w_stride, b_stride, shift, scale, raw ? zout : zstage};
+    hipError_t e;
     switch (hidden) {
-        case 64: return launch_fused_h<64>(m, members, n, ld, rho, T, Y, a, raw, stream);
-        case 128: return launch_fused_h<128>(m, members, n, ld, rho, T, Y, a, raw, stream);
-        default: return launch_fused_h<256>(m, members, n, ld, rho, T, Y, a, raw, stream);
+        case 64: e = launch_fused_h<64>(m, members, n, ld, rho, T, Y, a, raw, stream); break;
+        case 128: e = launch_fused_h<128>(m, members, n, ld, rho, T, Y, a, raw, stream); break;
+        default: e = launch_fused_h<256>(m, members, n, ld, rho, T, Y, a, raw, stream);
+    }
+    if (e != hipSuccess || raw) return e;
+    switch (members) {
+        case 1: return launch_post_e<1>(m, n, ld, zstage, ts, tmu, tsig, thr_spread, thr_resid, wdot, flag, ind, stream);
+        case 2: return launch_post_e<2>(m, n, ld, zstage, ts, tmu, tsig, thr_spread, thr_resid, wdot, flag, ind, stream);
+        case 3: return launch_post_e<3>(m, n, ld, zstage, ts, tmu, tsig, thr_spread, thr_resid, wdot, flag, ind, stream);
+        default: return launch_post_e<4>(m, n, ld, zstage, ts, tmu, tsig, thr_spread, thr_resid, wdot, flag, ind, stream);
     }
 }
 

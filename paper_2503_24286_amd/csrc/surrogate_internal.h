@@ -26,15 +26,16 @@ int64_t packed_weight_elems(int hidden);
 hipError_t launch_pack(int hidden, int members, int64_t w_total, int64_t b_total,
                        const uint16_t* W, const float* b, uint16_t* wp, float* bp,
                        hipStream_t stream);
-// zout == nullptr: evaluation (wdot, flag, optional ind); otherwise the raw
-// member outputs [members][n][64]
+// zout == nullptr: evaluation (wdot, flag, optional ind), the member outputs
+// staged in zstage [members][S][n]; otherwise the raw member outputs
+// [members][n][64] into zout
 hipError_t launch_fused(const pyro_mech* m, int hidden, int members, int64_t n, int64_t ld,
                         const double* rho, const double* T, const double* Y,
                         const uint16_t* wp, const float* bp, int64_t w_stride, int64_t b_stride,
                         const float* shift, const float* scale, const double* ts,
                         const double* tmu, const double* tsig, double thr_spread,
                         double thr_resid, double* wdot, uint8_t* flag, double* ind, float* zout,
-                        hipStream_t stream);
+                        float* zstage, hipStream_t stream);
 int64_t compaction_blocks(int64_t n);
 hipError_t launch_compaction(int64_t n, const uint8_t* flag, int64_t* counts, int64_t* total,
                              int64_t* idx, hipStream_t stream);
