@@ -566,7 +566,9 @@ def main():
                      | _lib.PYRO_WDOT_MFMA_THIRD_BODY | _lib.PYRO_WDOT_MFMA_NET_RATES),
                     ("reaction_equilibrium_third_body_on_mfma",
                      _lib.PYRO_WDOT_REACTION_EQUILIBRIUM | _lib.PYRO_WDOT_MFMA_THIRD_BODY),
-                    ("log_space", _lib.PYRO_WDOT_LOG_SPACE)):
+                    ("log_space", _lib.PYRO_WDOT_LOG_SPACE),
+                    ("log_space_log_products_on_mfma",
+                     _lib.PYRO_WDOT_LOG_SPACE | _lib.PYRO_WDOT_MFMA_LOG_PRODUCTS)):
         gm.wdot_variant = v
         variant_ms[name] = round(_time_ms(
             lambda: pyro.production_rates(gm, rho, T_out, Y_d, out=w2), 3, stream), 4)

@@ -91,7 +91,15 @@ enum pyro_wdot_variant {
      * reactions, ln(P_r/(1+P_r)) + ln F for falloff), so no intermediate
      * overflows before the rate itself; LDS rows hold C and ln C.  Every
      * PYRO_F32 call uses this form. */
-    PYRO_WDOT_LOG_SPACE = 8
+    PYRO_WDOT_LOG_SPACE = 8,
+    /* flag of PYRO_WDOT_LOG_SPACE only (FP64): the stoichiometric log sums
+     * sum_k nu'_kj ln C_k and sum_k nu''_kj ln C_k of a chunk of reactions
+     * over the 64-cell tile as dense products ln C [cells x S] nu [S x slots]
+     * on the FP64 matrix cores (v_mfma_f64_16x16x4f64), ln 0 floored at
+     * -1e30, instead of the per-reaction sums of LDS reads; reads back as
+     * PYRO_WDOT_LOG_SPACE | PYRO_WDOT_REACTION_EQUILIBRIUM |
+     * PYRO_WDOT_MFMA_LOG_PRODUCTS */
+    PYRO_WDOT_MFMA_LOG_PRODUCTS = 16
 };
 
 typedef struct pyro_mech pyro_mech;
@@ -131,8 +139,9 @@ PYRO_API void pyro_mech_free(pyro_mech* mech);
 PYRO_API int pyro_mech_get_info(const pyro_mech* mech, pyro_mech_info* info);
 /* Selects the production-rate kernel variant (enum pyro_wdot_variant, an
  * equilibrium variant optionally or-ed with PYRO_WDOT_MFMA_THIRD_BODY and
- * PYRO_WDOT_MFMA_NET_RATES, or PYRO_WDOT_LOG_SPACE, which reads back as
- * PYRO_WDOT_LOG_SPACE | PYRO_WDOT_REACTION_EQUILIBRIUM) used by FP64
+ * PYRO_WDOT_MFMA_NET_RATES, or PYRO_WDOT_LOG_SPACE optionally or-ed with
+ * PYRO_WDOT_MFMA_LOG_PRODUCTS, which reads back with
+ * PYRO_WDOT_REACTION_EQUILIBRIUM added) used by FP64
  * pyro_production_rates calls and the surrogate's fallback.  The loader picks the
  * species variant when its LDS tile fits and the reaction variant otherwise;
  * PYRO_E_UNSUPPORTED if the requested variant cannot run this mechanism.

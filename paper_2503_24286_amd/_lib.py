@@ -26,6 +26,7 @@ PYRO_WDOT_REACTION_EQUILIBRIUM = 1
 PYRO_WDOT_MFMA_THIRD_BODY = 2
 PYRO_WDOT_MFMA_NET_RATES = 4
 PYRO_WDOT_LOG_SPACE = 8
+PYRO_WDOT_MFMA_LOG_PRODUCTS = 16
 PYRO_REACTOR_RK4 = 0
 PYRO_REACTOR_CN = 1
 

@@ -99,16 +99,24 @@ int pyro_mech_set_wdot_variant(pyro_mech* m, int variant) {
     clear_error();
     if (!m) return fail(PYRO_E_ARG, "null mechanism handle");
     if (variant < 0 || variant > (PYRO_WDOT_REACTION_EQUILIBRIUM | PYRO_WDOT_MFMA_THIRD_BODY |
-                                  PYRO_WDOT_MFMA_NET_RATES | PYRO_WDOT_LOG_SPACE))
+                                  PYRO_WDOT_MFMA_NET_RATES | PYRO_WDOT_LOG_SPACE |
+                                  PYRO_WDOT_MFMA_LOG_PRODUCTS))
         return fail(PYRO_E_ARG, "unknown production-rate variant");
+    if ((variant & PYRO_WDOT_MFMA_LOG_PRODUCTS) && !(variant & PYRO_WDOT_LOG_SPACE))
+        return fail(PYRO_E_ARG, "PYRO_WDOT_MFMA_LOG_PRODUCTS is a flag of PYRO_WDOT_LOG_SPACE");
     if (variant & PYRO_WDOT_LOG_SPACE) {
         // the log-space form implies the reaction-equilibrium coefficients
         if (variant & (PYRO_WDOT_MFMA_THIRD_BODY | PYRO_WDOT_MFMA_NET_RATES))
-            return fail(PYRO_E_UNSUPPORTED, "the log-space form has no matrix-core flags");
+            return fail(PYRO_E_UNSUPPORTED, "the log-space form has no third-body or net-rate "
+                                            "matrix-core flags");
         if (!log_space_supported(m, 8))
             return fail(PYRO_E_UNSUPPORTED, m->kc_ok ? "mechanism too large for the log-space tile"
                                                      : "reactions mix species with different NASA7 T_mid");
-        m->wdot_variant = PYRO_WDOT_LOG_SPACE | PYRO_WDOT_REACTION_EQUILIBRIUM;
+        if ((variant & PYRO_WDOT_MFMA_LOG_PRODUCTS) && !log_products_supported(m))
+            return fail(PYRO_E_UNSUPPORTED, "mechanism too large for the log-space tile with its "
+                                            "log products on the matrix cores");
+        m->wdot_variant = PYRO_WDOT_LOG_SPACE | PYRO_WDOT_REACTION_EQUILIBRIUM |
+                          (variant & PYRO_WDOT_MFMA_LOG_PRODUCTS);
         return PYRO_OK;
     }
     const bool rkc = variant & PYRO_WDOT_REACTION_EQUILIBRIUM;

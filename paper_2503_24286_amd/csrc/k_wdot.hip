@@ -122,13 +122,16 @@ __device__ inline real lds_lnc(const unsigned char* lds, int off, int lane) {
     return reinterpret_cast<const real*>(lds + (off >> sh))[kTile + lane];
 }
 
-// Log-space rate of progress (see the LOG variant above).
-template <typename real>
+// Log-space rate of progress (see the LOG variant above).  LP: the sums
+// sum_k nu'_kj ln C_k and sum_k nu''_kj ln C_k come from the tile's
+// matrix-core contraction (lpf, lpr: this lane's values for the reaction).
+template <typename real, bool LP = false>
 __device__ inline real rate_of_progress_log(const DevMech& m, const RxnRec& r,
                                             const double* __restrict__ params,
                                             const unsigned char* lds, int lane, real lnk,
                                             real M, real Tc, real lnT, real invT, real invRT,
-                                            real ln_rtp, cptr<double> kc) {
+                                            real ln_rtp, cptr<double> kc, real lpf = 0,
+                                            real lpr = 0) {
     if (r.cls >= kLindemann) {
         // ln P_r = ln k0 + ln [M] - ln k_inf; ln k += ln(P_r/(1+P_r)) + ln F
         const real lpr = log_arrhenius<real>(params, m.R + r.fo, lnT, invRT) + log(M) - lnk;
@@ -153,18 +156,28 @@ __device__ inline real rate_of_progress_log(const DevMech& m, const RxnRec& r,
         }
         lnk += log_blend(lpr) + lnF;
     }
-    real xf = lnk + lds_lnc<real>(lds, r.r[0], lane);
-    if (r.nr > 1) {
-        xf += lds_lnc<real>(lds, r.r[1], lane);
-        if (r.nr > 2) xf += lds_lnc<real>(lds, r.r[2], lane);
+    real xf = lnk;
+    if constexpr (LP) {
+        xf += lpf;
+    } else {
+        xf += lds_lnc<real>(lds, r.r[0], lane);
+        if (r.nr > 1) {
+            xf += lds_lnc<real>(lds, r.r[1], lane);
+            if (r.nr > 2) xf += lds_lnc<real>(lds, r.r[2], lane);
+        }
     }
     const real lm = r.cls == kThirdBody ? log(M) : real(0);
     real q = exp(xf + lm);
     if (r.rev) {
-        real xr = lnk + real(r.dnu) * ln_rtp + lds_lnc<real>(lds, r.p[0], lane);
-        if (r.np > 1) {
-            xr += lds_lnc<real>(lds, r.p[1], lane);
-            if (r.np > 2) xr += lds_lnc<real>(lds, r.p[2], lane);
+        real xr = lnk + real(r.dnu) * ln_rtp;
+        if constexpr (LP) {
+            xr += lpr;
+        } else {
+            xr += lds_lnc<real>(lds, r.p[0], lane);
+            if (r.np > 1) {
+                xr += lds_lnc<real>(lds, r.p[1], lane);
+                if (r.np > 2) xr += lds_lnc<real>(lds, r.p[2], lane);
+            }
         }
         const double lo[7] = {kc[0], kc[1], kc[2], kc[3], kc[4], kc[5], kc[6]};
         const double hi[7] = {kc[7], kc[8], kc[9], kc[10], kc[11], kc[12], kc[13]};
@@ -272,14 +285,17 @@ __device__ inline double rate_of_progress(const DevMech& m, const RxnRec& r,
 typedef double d4 __attribute__((ext_vector_type(4)));
 
 // real: the arithmetic and cell-array type (double, or float with LOG).
-template <typename real, int WAVES, int MAXOWN, int MAXPD, bool RKC, bool MM, bool NQ, bool LOG>
-__global__ __launch_bounds__(WAVES * 64) void wdot_kernel(
+template <typename real, int WAVES, int MAXOWN, int MAXPD, bool RKC, bool MM, bool NQ, bool LOG,
+          bool LP = false>
+__global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(LP ? 4 : 1))) void wdot_kernel(
     DevMech m, int64_t n, int64_t ld, const real* __restrict__ rho,
     const real* __restrict__ T, const real* __restrict__ Y,
     real* __restrict__ wdot, const double* __restrict__ params,
     const int64_t* __restrict__ n_dev) {
     static_assert(!LOG || RKC, "the log-space form uses the combined Gibbs coefficients");
     static_assert(sizeof(real) == 8 || (LOG && !MM && !NQ), "float runs the log-space form only");
+    static_assert(!LP || (LOG && sizeof(real) == 8 && !MM && !NQ),
+                  "the matrix-core log products are an FP64 log-space form");
     // byte offsets in the tables are given for double rows and slots
     constexpr int sh = sizeof(real) == 4 ? 1 : 0;
     extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
@@ -320,7 +336,13 @@ __global__ __launch_bounds__(WAVES * 64) void wdot_kernel(
             const real Ck = rc * fmax(y[i], real(0)) * real(s.inv_w);
             real* row = reinterpret_cast<real*>(lds + k * rowb) + lane;
             row[0] = Ck;
-            if constexpr (LOG) {
+            if constexpr (LP) {
+                // a finite floor for ln 0: the dense contraction multiplies
+                // every ln C by the (mostly zero) coefficients
+                // (a select, not fmax: a NaN stays NaN)
+                const real lc = log(Ck);
+                row[kTile] = lc < real(-kLnFloor) ? real(-kLnFloor) : lc;
+            } else if constexpr (LOG) {
                 row[kTile] = log(Ck);
             } else if constexpr (!RKC) {
                 // both ranges from scalar loads, then a per-lane select of the
@@ -338,6 +360,10 @@ __global__ __launch_bounds__(WAVES * 64) void wdot_kernel(
     unsigned char* qbase = lds + size_t(m.S) * rowb;
     constexpr int qbuf = WAVES * kRxnPerWave * kTile * sizeof(real);   // bytes per chunk buffer
     double* Ml = reinterpret_cast<double*>(qbase + 2 * qbuf);  // MM: [n_pd16][64]
+    // LP: sum_k nu''_kj ln C_k of the chunk's slots [slot][64]; the forward
+    // sums go into the chunk buffer itself, each slot overwritten by its q
+    // by the wave that read it
+    double* lpr_l = reinterpret_cast<double*>(qbase + 2 * qbuf);
     if constexpr (MM) {
         // ---- the tile's third-body concentrations on the matrix cores: wave w
         // takes the 16-cell x 16-reaction output blocks w, w + 8, ...
@@ -408,6 +434,32 @@ __global__ __launch_bounds__(WAVES * 64) void wdot_kernel(
         // (8 waves: loaded before the rates are evaluated; 16 waves, with
         // three blocks of eight K-steps, after them to spare registers)
         if constexpr (NQ && WAVES == kWaves) load_nub();
+        if constexpr (LP) {
+            // the chunk's log products on the matrix cores: D[cell][slot] =
+            // sum_k ln C[cell][k] nu[k][slot] for nu' (side 0, into the chunk
+            // buffer) and nu'' (side 1); wave w computes the 16-cell x
+            // 16-slot block of cell block w & 3, slot block (w >> 2) % NSB,
+            // side (w >> 2) / NSB
+            constexpr int NSB = WAVES * kRxnPerWave / 16;
+            const int cb = w & 3, sb = (w >> 2) % NSB, side = (w >> 2) / NSB;
+            const double* bf = m.lp_frag + ((size_t(ch) * 2 + side) * NSB + sb) * m.lp_nks * 64 + lane;
+            d4 acc4 = {0.0, 0.0, 0.0, 0.0};
+            for (int kk = 0; kk < m.lp_nks; ++kk) {
+                const int k = 4 * kk + (lane >> 4);
+                // zero beyond S (the B fragments are zero there too, but LDS
+                // past the rows is not)
+                const double a = k < m.S
+                    ? reinterpret_cast<const double*>(lds + k * kRow)[kTile + 16 * cb + (lane & 15)]
+                    : 0.0;
+                acc4 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bf[size_t(kk) * 64], acc4, 0, 0, 0);
+            }
+            // D: register i of lane l is cell 16 cb + 4 i + l/16, slot 16 sb + l%16
+            double* dst = side == 0 ? reinterpret_cast<double*>(qb) : lpr_l;
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                dst[(16 * sb + (lane & 15)) * kTile + 16 * cb + 4 * i + (lane >> 4)] = acc4[i];
+            __syncthreads();
+        }
         const RxnRec* rb = m.rxn + (size_t(ch) * WAVES + w) * kRxnPerWave;
         const RxnRec r0 = rb[0];
         const RxnRec r1 = rb[1];
@@ -425,12 +477,20 @@ __global__ __launch_bounds__(WAVES * 64) void wdot_kernel(
         if constexpr (LOG) {
             const real lk0 = log_arrhenius<real>(params, r0.prow, lnT, invRT);
             const real lk1 = log_arrhenius<real>(params, r1.prow, lnT, invRT);
+            real f0 = 0, f1 = 0, b0 = 0, b1 = 0;
+            if constexpr (LP) {
+                // this wave's slots, read before its q overwrites them
+                f0 = *reinterpret_cast<const real*>(qb + r0.qoff + lane * 8);
+                f1 = *reinterpret_cast<const real*>(qb + r1.qoff + lane * 8);
+                b0 = *reinterpret_cast<const real*>(reinterpret_cast<const unsigned char*>(lpr_l) + r0.qoff + lane * 8);
+                b1 = *reinterpret_cast<const real*>(reinterpret_cast<const unsigned char*>(lpr_l) + r1.qoff + lane * 8);
+            }
             if (r0.cls != kNoReaction)
-                q0 = rate_of_progress_log<real>(m, r0, params, lds, lane, lk0, M0, Tc, lnT, invT,
-                                                invRT, ln_rtp, kc);
+                q0 = rate_of_progress_log<real, LP>(m, r0, params, lds, lane, lk0, M0, Tc, lnT, invT,
+                                                    invRT, ln_rtp, kc, f0, b0);
             if (r1.cls != kNoReaction)
-                q1 = rate_of_progress_log<real>(m, r1, params, lds, lane, lk1, M1, Tc, lnT, invT,
-                                                invRT, ln_rtp, kc + 16);
+                q1 = rate_of_progress_log<real, LP>(m, r1, params, lds, lane, lk1, M1, Tc, lnT, invT,
+                                                    invRT, ln_rtp, kc + 16, f1, b1);
         } else {
             // both Arrhenius exponentials in one block, so they interleave
             const double kf0 = exp(log_arrhenius<double>(params, r0.prow, lnT, invRT));
@@ -515,13 +575,14 @@ __global__ __launch_bounds__(WAVES * 64) void wdot_kernel(
     }
 }
 
-template <typename real, int WAVES, int MAXOWN, int MAXPD, bool RKC, bool MM, bool NQ, bool LOG>
+template <typename real, int WAVES, int MAXOWN, int MAXPD, bool RKC, bool MM, bool NQ, bool LOG,
+          bool LP = false>
 hipError_t launch_k(const pyro_mech* m, int64_t n, int64_t ld, const real* rho, const real* T,
                     const real* Y, real* wdot, const double* params, hipStream_t stream,
                     const int64_t* n_dev) {
-    const size_t lds = production_rates_lds_bytes(m, RKC, MM, LOG, sizeof(real));
+    const size_t lds = production_rates_lds_bytes(m, RKC, MM, LOG, sizeof(real), LP);
     const int64_t blocks = (n + kTile - 1) / kTile;
-    hipLaunchKernelGGL((wdot_kernel<real, WAVES, MAXOWN, MAXPD, RKC, MM, NQ, LOG>),
+    hipLaunchKernelGGL((wdot_kernel<real, WAVES, MAXOWN, MAXPD, RKC, MM, NQ, LOG, LP>),
                        dim3(unsigned(blocks)), dim3(WAVES * 64), lds, stream, m->dev, n, ld, rho,
                        T, Y, wdot, params ? params : m->dev.params, n_dev);
     return hipGetLastError();
@@ -530,42 +591,43 @@ hipError_t launch_k(const pyro_mech* m, int64_t n, int64_t ld, const real* rho, 
 // Kernel instances: (type, wavefronts, species owned per wave, [M] slots per
 // wave, variant).  With 2 kWaves wavefronts (large mechanisms, reaction
 // variant only) a wave owns at most 16 species.
-template <typename real, int WAVES, int MAXOWN, int MAXPD, bool RKC, bool MM, bool NQ, bool LOG>
+template <typename real, int WAVES, int MAXOWN, int MAXPD, bool RKC, bool MM, bool NQ, bool LOG,
+          bool LP = false>
 hipError_t set_lds(int bytes) {
     return hipFuncSetAttribute(
-        reinterpret_cast<const void*>(&wdot_kernel<real, WAVES, MAXOWN, MAXPD, RKC, MM, NQ, LOG>),
+        reinterpret_cast<const void*>(&wdot_kernel<real, WAVES, MAXOWN, MAXPD, RKC, MM, NQ, LOG, LP>),
         hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
 // the NQ instances exist for at most 16 species per wave (NQ needs S <= 64)
-template <typename real, int MAXPD, bool RKC, bool MM, bool NQ, bool LOG>
+template <typename real, int MAXPD, bool RKC, bool MM, bool NQ, bool LOG, bool LP = false>
 hipError_t dispatch_own(const pyro_mech* m, int64_t n, int64_t ld, const real* r, const real* t,
                         const real* y, real* o, const double* params, hipStream_t stream,
                         const int64_t* nd) {
     if constexpr (RKC) {
         if (m->fw_waves != kWaves) {
             if (!NQ && m->max_own <= 8)
-                return launch_k<real, 2 * kWaves, 8, MAXPD, RKC, MM, false, LOG>(m, n, ld, r, t, y, o, params, stream, nd);
-            return launch_k<real, 2 * kWaves, 16, MAXPD, RKC, MM, NQ, LOG>(m, n, ld, r, t, y, o, params, stream, nd);
+                return launch_k<real, 2 * kWaves, 8, MAXPD, RKC, MM, false, LOG, LP>(m, n, ld, r, t, y, o, params, stream, nd);
+            return launch_k<real, 2 * kWaves, 16, MAXPD, RKC, MM, NQ, LOG, LP>(m, n, ld, r, t, y, o, params, stream, nd);
         }
     }
-    if (m->max_own <= 8) return launch_k<real, kWaves, 8, MAXPD, RKC, MM, NQ, LOG>(m, n, ld, r, t, y, o, params, stream, nd);
+    if (m->max_own <= 8) return launch_k<real, kWaves, 8, MAXPD, RKC, MM, NQ, LOG, LP>(m, n, ld, r, t, y, o, params, stream, nd);
     if (NQ || m->max_own <= 16)
-        return launch_k<real, kWaves, 16, MAXPD, RKC, MM, NQ, LOG>(m, n, ld, r, t, y, o, params, stream, nd);
-    if (m->max_own <= 32) return launch_k<real, kWaves, 32, MAXPD, RKC, MM, false, LOG>(m, n, ld, r, t, y, o, params, stream, nd);
-    return launch_k<real, kWaves, 64, MAXPD, RKC, MM, false, LOG>(m, n, ld, r, t, y, o, params, stream, nd);
+        return launch_k<real, kWaves, 16, MAXPD, RKC, MM, NQ, LOG, LP>(m, n, ld, r, t, y, o, params, stream, nd);
+    if (m->max_own <= 32) return launch_k<real, kWaves, 32, MAXPD, RKC, MM, false, LOG, LP>(m, n, ld, r, t, y, o, params, stream, nd);
+    return launch_k<real, kWaves, 64, MAXPD, RKC, MM, false, LOG, LP>(m, n, ld, r, t, y, o, params, stream, nd);
 }
 
-template <typename real, bool RKC, bool MM, bool NQ, bool LOG>
+template <typename real, bool RKC, bool MM, bool NQ, bool LOG, bool LP = false>
 hipError_t set_lds_variant(const pyro_mech* m, int bytes) {
     hipError_t e = hipSuccess;
     if constexpr (RKC) {
         if (m->fw_waves != kWaves) {
             const hipError_t big[] = {
-                NQ ? hipSuccess : set_lds<real, 2 * kWaves, 8, 8, RKC, MM, false, LOG>(bytes),
-                set_lds<real, 2 * kWaves, 16, 8, RKC, MM, NQ, LOG>(bytes),
-                MM || NQ ? hipSuccess : set_lds<real, 2 * kWaves, 8, 16, RKC, MM, false, LOG>(bytes),
-                MM ? hipSuccess : set_lds<real, 2 * kWaves, 16, 16, RKC, MM, NQ, LOG>(bytes)};
+                NQ ? hipSuccess : set_lds<real, 2 * kWaves, 8, 8, RKC, MM, false, LOG, LP>(bytes),
+                set_lds<real, 2 * kWaves, 16, 8, RKC, MM, NQ, LOG, LP>(bytes),
+                MM || NQ ? hipSuccess : set_lds<real, 2 * kWaves, 8, 16, RKC, MM, false, LOG, LP>(bytes),
+                MM ? hipSuccess : set_lds<real, 2 * kWaves, 16, 16, RKC, MM, NQ, LOG, LP>(bytes)};
             for (hipError_t x : big)
                 if (x != hipSuccess) e = x;
             return e;
@@ -573,20 +635,20 @@ hipError_t set_lds_variant(const pyro_mech* m, int bytes) {
     }
     // the MFMA third-body variant holds no per-wave [M] slots: one MAXPD instance
     const hipError_t all[] = {
-        set_lds<real, kWaves, 8, 8, RKC, MM, NQ, LOG>(bytes),
-        set_lds<real, kWaves, 16, 8, RKC, MM, NQ, LOG>(bytes),
-        NQ ? hipSuccess : set_lds<real, kWaves, 32, 8, RKC, MM, false, LOG>(bytes),
-        NQ ? hipSuccess : set_lds<real, kWaves, 64, 8, RKC, MM, false, LOG>(bytes),
-        MM ? hipSuccess : set_lds<real, kWaves, 8, 16, RKC, MM, NQ, LOG>(bytes),
-        MM ? hipSuccess : set_lds<real, kWaves, 16, 16, RKC, MM, NQ, LOG>(bytes),
-        MM || NQ ? hipSuccess : set_lds<real, kWaves, 32, 16, RKC, MM, false, LOG>(bytes),
-        MM || NQ ? hipSuccess : set_lds<real, kWaves, 64, 16, RKC, MM, false, LOG>(bytes)};
+        set_lds<real, kWaves, 8, 8, RKC, MM, NQ, LOG, LP>(bytes),
+        set_lds<real, kWaves, 16, 8, RKC, MM, NQ, LOG, LP>(bytes),
+        NQ ? hipSuccess : set_lds<real, kWaves, 32, 8, RKC, MM, false, LOG, LP>(bytes),
+        NQ ? hipSuccess : set_lds<real, kWaves, 64, 8, RKC, MM, false, LOG, LP>(bytes),
+        MM ? hipSuccess : set_lds<real, kWaves, 8, 16, RKC, MM, NQ, LOG, LP>(bytes),
+        MM ? hipSuccess : set_lds<real, kWaves, 16, 16, RKC, MM, NQ, LOG, LP>(bytes),
+        MM || NQ ? hipSuccess : set_lds<real, kWaves, 32, 16, RKC, MM, false, LOG, LP>(bytes),
+        MM || NQ ? hipSuccess : set_lds<real, kWaves, 64, 16, RKC, MM, false, LOG, LP>(bytes)};
     for (hipError_t x : all)
         if (x != hipSuccess) e = x;
     return e;
 }
 
-template <typename real, bool RKC, bool MM, bool NQ, bool LOG>
+template <typename real, bool RKC, bool MM, bool NQ, bool LOG, bool LP = false>
 hipError_t dispatch_variant(const pyro_mech* m, int64_t n, int64_t ld, const void* r,
                             const void* t, const void* y, void* o, const double* params,
                             hipStream_t stream, const int64_t* nd) {
@@ -595,19 +657,28 @@ hipError_t dispatch_variant(const pyro_mech* m, int64_t n, int64_t ld, const voi
     const real* yy = static_cast<const real*>(y);
     real* oo = static_cast<real*>(o);
     if (MM || m->max_pdw <= 8)
-        return dispatch_own<real, 8, RKC, MM, NQ, LOG>(m, n, ld, rr, tt, yy, oo, params, stream, nd);
-    return dispatch_own<real, 16, RKC, MM, NQ, LOG>(m, n, ld, rr, tt, yy, oo, params, stream, nd);
+        return dispatch_own<real, 8, RKC, MM, NQ, LOG, LP>(m, n, ld, rr, tt, yy, oo, params, stream, nd);
+    return dispatch_own<real, 16, RKC, MM, NQ, LOG, LP>(m, n, ld, rr, tt, yy, oo, params, stream, nd);
 }
 
 }  // namespace
 
 size_t production_rates_lds_bytes(const pyro_mech* m, bool reaction_equilibrium,
-                                  bool mfma_third_body, bool log_space, int real_bytes) {
+                                  bool mfma_third_body, bool log_space, int real_bytes,
+                                  bool log_products) {
     // species rows: C and G (species variant), C (reaction variant) or C and
-    // ln C (log-space), 64 values each; two chunk buffers of rates; [M] block
+    // ln C (log-space), 64 values each; two chunk buffers of rates; [M]
+    // block; the reverse-side log products of a chunk
     const size_t row = size_t(kTile) * real_bytes * (log_space || !reaction_equilibrium ? 2 : 1);
-    return size_t(m->S) * row + 2 * size_t(m->fw_waves) * kRxnPerWave * kTile * real_bytes +
-           (mfma_third_body ? size_t((m->n_tb + m->n_fo + 15) / 16 * 16) * kTile * 8 : 0);
+    const size_t chunk = size_t(m->fw_waves) * kRxnPerWave * kTile * real_bytes;
+    return size_t(m->S) * row + 2 * chunk +
+           (mfma_third_body ? size_t((m->n_tb + m->n_fo + 15) / 16 * 16) * kTile * 8 : 0) +
+           (log_products ? chunk : 0);
+}
+
+bool log_products_supported(const pyro_mech* m) {
+    return m->kc_ok && m->dev.lp_nks > 0 &&
+           production_rates_lds_bytes(m, true, false, true, 8, true) <= 160 * 1024;
 }
 
 bool log_space_supported(const pyro_mech* m, int real_bytes) {
@@ -643,6 +714,11 @@ hipError_t prepare_production_rates(const pyro_mech* m) {
             m, int(production_rates_lds_bytes(m, true, false, true, 4)));
         if (x != hipSuccess) e = x;
     }
+    if (log_products_supported(m)) {
+        const hipError_t x = set_lds_variant<double, true, false, false, true, true>(
+            m, int(production_rates_lds_bytes(m, true, false, true, 8, true)));
+        if (x != hipSuccess) e = x;
+    }
     return e;
 }
 
@@ -667,6 +743,7 @@ hipError_t launch_production_rates(const pyro_mech* m, int64_t n, int64_t ld, in
         case 6: return dispatch_variant<double, false, true, true, false>(m, n, ld, r, t, y, o, params, stream, nd);
         case 7: return dispatch_variant<double, true, true, true, false>(m, n, ld, r, t, y, o, params, stream, nd);
         case 9: return dispatch_variant<double, true, false, false, true>(m, n, ld, r, t, y, o, params, stream, nd);
+        case 25: return dispatch_variant<double, true, false, false, true, true>(m, n, ld, r, t, y, o, params, stream, nd);
         default: return dispatch_variant<double, false, false, false, false>(m, n, ld, r, t, y, o, params, stream, nd);
     }
 }

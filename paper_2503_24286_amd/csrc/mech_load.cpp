@@ -644,6 +644,26 @@ int load_mechanism(const char* path, pyro_mech** out) {
                 }
             }
 
+    // B fragments of nu' and nu'' per forward chunk for the log-space form's
+    // matrix-core log products, [chunk][side][slot block][K-step][lane] =
+    // nu[4 kk + l/16][slot 16 sb + l%16]; built when that form can run
+    const int lp_nsb = cslots / 16, lp_nks = (S + 3) / 4;
+    const bool lp_table = m->kc_ok;
+    std::vector<double> lp_frag(
+        lp_table ? size_t(std::max(n_chunks, 1)) * 2 * lp_nsb * lp_nks * 64 : 1, 0.0);
+    if (lp_table)
+        for (int c = 0; c < n_chunks; ++c)
+            for (int slot = 0; slot < cslots; ++slot) {
+                const RxnRec& r = recs[size_t(c) * cslots + slot];
+                if (r.cls == kNoReaction) continue;
+                const int j = r.prow;
+                for (int side = 0; side < 2; ++side)
+                    for (int k : side == 0 ? reac[j] : prod[j]) {
+                        const int kk = k / 4, l = (k % 4) * 16 + slot % 16;
+                        lp_frag[((((size_t(c) * 2 + side) * lp_nsb + slot / 16) * lp_nks + kk) * 64) + l] += 1.0;
+                    }
+            }
+
     // ---- one device allocation holding every table
     struct Part { const void* src; size_t bytes; size_t off; };
     std::vector<Part> parts = {
@@ -673,6 +693,7 @@ int load_mechanism(const char* path, pyro_mech** out) {
         {eps_frag.data(), eps_frag.size() * sizeof(double), 0},
         {veffo.data(), veffo.size() * sizeof(double), 0},
         {nu_frag.data(), nu_frag.size() * sizeof(double), 0},
+        {lp_frag.data(), lp_frag.size() * sizeof(double), 0},
     };
     size_t total = 0;
     for (auto& p : parts) {
@@ -743,6 +764,8 @@ int load_mechanism(const char* path, pyro_mech** out) {
     d.eps_frag = reinterpret_cast<const double*>(base + parts[23].off);
     v.effo = reinterpret_cast<const double*>(base + parts[24].off);
     d.nu_frag = reinterpret_cast<const double*>(base + parts[25].off);
+    d.lp_frag = reinterpret_cast<const double*>(base + parts[26].off);
+    d.lp_nks = lp_table ? lp_nks : 0;
     err = prepare_production_rates(m);
     if (err == hipSuccess) err = prepare_vjp(m);
     if (err != hipSuccess) {

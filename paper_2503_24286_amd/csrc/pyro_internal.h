@@ -170,9 +170,14 @@ struct DevMech {
     // [chunk][species block 0..3][K-step 0..3][lane] = nu[16 sb + l%16][reaction
     // in slot 4 kk + l/16] (zero for empty slots and species past S)
     const double* nu_frag;
+    // matrix-core log products (log-space FP64 variant): B fragments of nu'
+    // (side 0) and nu'' (side 1) per chunk, [chunk][side][slot block][K-step]
+    // [lane] = nu[4 kk + l/16][slot 16 sb + l%16] (zero for empty slots and
+    // species past S); lp_nks K-steps of 4 species (0: table not built)
+    const double* lp_frag;
     // surrogate
     int32_t E;                           // elements
-    int32_t pad2;
+    int32_t lp_nks;
     const double* comp;                  // [E][S] atoms of element e in species k
 };
 
@@ -252,10 +257,14 @@ hipError_t launch_internal_energy(const pyro_mech* m, int64_t n, int64_t ld,
 // LDS bytes the production-rate kernel needs for this mechanism.
 size_t production_rates_lds_bytes(const pyro_mech* m, bool reaction_equilibrium,
                                   bool mfma_third_body = false, bool log_space = false,
-                                  int real_bytes = 8);
+                                  int real_bytes = 8, bool log_products = false);
 // The log-space form (FP64 variant, and every FP32 call) can run this
 // mechanism: one T_mid per reaction and its rows fit the LDS tile.
 bool log_space_supported(const pyro_mech* m, int real_bytes);
+// The FP64 log-space form with its log products on the matrix cores fits.
+bool log_products_supported(const pyro_mech* m);
+// ln C floor of that form (0 * ln 0 would poison the dense contraction)
+constexpr double kLnFloor = 1e30;
 hipError_t prepare_production_rates(const pyro_mech* m);
 hipError_t launch_production_rates_vjp(const pyro_mech* m, int64_t n, int64_t ld,
                                        const double* rho, const double* T, const double* Y,

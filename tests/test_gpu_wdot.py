@@ -226,8 +226,14 @@ def test_variant_selection_errors(cfg3_mech):
     with pytest.raises(_lib.PyroError) as e:   # 160 (C, ln C) rows exceed the LDS
         gm.wdot_variant = _lib.PYRO_WDOT_LOG_SPACE
     assert e.value.code == _lib.PYRO_E_UNSUPPORTED
+    with pytest.raises(_lib.PyroError) as e:   # a flag of the log-space form only
+        gm.wdot_variant = _lib.PYRO_WDOT_MFMA_LOG_PRODUCTS
+    assert e.value.code == _lib.PYRO_E_ARG
     with pytest.raises(_lib.PyroError) as e:
-        gm.wdot_variant = 16
+        gm.wdot_variant = _lib.PYRO_WDOT_LOG_SPACE | _lib.PYRO_WDOT_MFMA_LOG_PRODUCTS
+    assert e.value.code == _lib.PYRO_E_UNSUPPORTED
+    with pytest.raises(_lib.PyroError) as e:
+        gm.wdot_variant = 32
     assert e.value.code == _lib.PYRO_E_ARG
     with pytest.raises(_lib.PyroError) as e:
         gm.wdot_variant = -1
@@ -261,6 +267,35 @@ def test_log_space_variant_matches_oracle(lib_mechs, cfg, n):
                     _lib.PYRO_WDOT_LOG_SPACE | _lib.PYRO_WDOT_MFMA_NET_RATES):
             with pytest.raises(_lib.PyroError):
                 gm.wdot_variant = bad
+    finally:
+        gm.wdot_variant = before
+
+
+@pytest.mark.parametrize("cfg,n", [(0, 1000), (1, 2000 + 45)])
+def test_log_products_on_mfma_match_oracle(lib_mechs, cfg, n):
+    """The log-space form with its stoichiometric log sums (sum_k nu'_kj ln C_k,
+    sum_k nu''_kj ln C_k) as dense products on the FP64 matrix cores, at the
+    FP64 parity bar, with the same degenerate states as the VALU form (ln 0
+    floored at -1e30 so that zero coefficients times it stay zero)."""
+    from paper_2503_24286_amd import _lib
+    torch, pyro, gms = lib_mechs
+    m = mechs.load_config(cfg)
+    gm = gms[cfg]
+    T, p, Y, rho = states(cfg, n, m.S, first=3333)
+    Y[:, :32] = 0.0
+    Y[min(5, m.S - 1), :32] = 1.0
+    Y[3, 32:64] = -1e-3
+    T[64:72] = m.T_mid[0]
+    before = gm.wdot_variant
+    try:
+        gm.wdot_variant = _lib.PYRO_WDOT_LOG_SPACE | _lib.PYRO_WDOT_MFMA_LOG_PRODUCTS
+        assert gm.wdot_variant == (_lib.PYRO_WDOT_LOG_SPACE | _lib.PYRO_WDOT_REACTION_EQUILIBRIUM
+                                   | _lib.PYRO_WDOT_MFMA_LOG_PRODUCTS)
+        announce(f"wdot log products on MFMA cfg{cfg} n={n}")
+        w = _run(torch, pyro, gm, rho, T, Y)
+        r = assert_wdot_parity(m, rho, T, Y, w)
+        record(f"wdot log products on MFMA cfg{cfg} n={n}", "omega scaled", r["scaled"].max(),
+               1e-12)
     finally:
         gm.wdot_variant = before
 
