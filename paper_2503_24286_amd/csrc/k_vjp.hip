@@ -268,6 +268,16 @@ __device__ inline double cp_poly(const double* a, double T) {
     return a[0] + T * (a[1] + T * (a[2] + T * (a[3] + T * a[4])));
 }
 
+// The schedule a launch runs: the reverse sweep's, or a Jacobian row's.
+template <int JAC>
+__device__ inline DevSched sched_of(const DevMech& m, int unit) {
+    if constexpr (JAC != 0) {
+        return m.jac_rows[unit];
+    } else {
+        return m.vjp;
+    }
+}
+
 // WITH_W: also the net production rates, gathered from a third plane (q).
 // JAC (0: the VJP; 1, 2: one row of the chemical Jacobian): the cotangent is
 // W_unit on species ``unit`` and zero elsewhere (not read from wbar), so Ybar
@@ -288,7 +298,10 @@ __global__ __launch_bounds__(kVjpWaves * 64) void vjp_kernel(
     static_assert(JAC == 0 || !WITH_W, "Jacobian rows do not return omega");
     constexpr int kBuf = (WITH_W ? 3 : 2) * kPlane;   // one chunk buffer: a, b (, q) planes
     extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
-    const DevSched& sc = m.vjp;
+    // Jacobian rows run the row's own schedule: only the reactions with a
+    // nonzero net coefficient of the unit species (the others have a zero
+    // cotangent), packed into as few chunks as they fill
+    const DevSched sc = sched_of<JAC>(m, unit);
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     unsigned char* bufs = lds + size_t(m.S) * kVRow;
@@ -299,9 +312,7 @@ __global__ __launch_bounds__(kVjpWaves * 64) void vjp_kernel(
     const int n_rows = m.R + m.n_fo;
     if (JAC == 0)
         for (int i = threadIdx.x; i < 3 * n_rows; i += kVjpWaves * 64) pacc[i] = 0.0;
-    // JAC: byte offset of the unit species' row (compared with the reaction
-    // records' participant offsets) and its molar mass
-    const int unit_off = unit * kVRow;
+    // JAC: the unit species' molar mass
     const double w_unit = JAC ? cst(m.w)[unit >= 0 ? unit : 0] : 0.0;
 
     const int nown = cst(sc.n_own)[w];
@@ -391,25 +402,7 @@ __global__ __launch_bounds__(kVjpWaves * 64) void vjp_kernel(
             unsigned char* plane_b = plane_a + kPlane;
             unsigned char* plane_q = plane_b + kPlane;
             const RxnRec r = cst(sc.rxn)[size_t(ch) * kVjpWaves + w];
-            // JAC: a reaction without the unit species has qbar = 0 and adds
-            // nothing; its slots are zeroed and its [M] slot consumed
-            bool skip = false;
-            if constexpr (JAC != 0) {
-                skip = true;
-                for (int i = 0; i < kMaxSide; ++i) {
-                    if (i < r.nr && r.r[i] == unit_off) skip = false;
-                    if (i < r.np && r.p[i] == unit_off) skip = false;
-                }
-                if (skip && r.cls != kNoReaction) {
-                    *reinterpret_cast<double*>(plane_a + r.qoff + lane * 8) = 0.0;
-                    *reinterpret_cast<double*>(plane_b + r.qoff + lane * 8) = 0.0;
-                    if (r.cls >= kThirdBody) {
-                        pop_front(Mr);
-                        Mr[MAXPD - 1] = 0.0;
-                    }
-                }
-            }
-            if (r.cls != kNoReaction && !skip) {
+            if (r.cls != kNoReaction) {
                 const double M = r.cls >= kThirdBody ? pop_front(Mr) : 1.0;
                 const RevOut o = reaction_vjp(m, r, params, lds, lane, M, cs);
                 *reinterpret_cast<double*>(plane_a + r.qoff + lane * 8) = o.a;
@@ -484,8 +477,13 @@ __global__ __launch_bounds__(kVjpWaves * 64) void vjp_kernel(
         }
 
         // ---- Mbar of this wave's third-body reactions into LDS, once every
-        // wave is done with the chunk buffers
+        // wave is done with the chunk buffers (Jacobian rows: the rows of
+        // third-body reactions outside the row's schedule are zero)
         __syncthreads();
+        if constexpr (JAC != 0) {
+            for (int i = threadIdx.x; i < m.n_pd * kTile; i += kVjpWaves * 64) mbar[i] = 0.0;
+            __syncthreads();
+        }
         {
             const cptr<int32_t> pl = cst(sc.pd_list) + w * kMaxPd;
 #pragma unroll

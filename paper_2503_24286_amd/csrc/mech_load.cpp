@@ -338,6 +338,79 @@ int build_schedule(const SchedInput& in, int waves, int rpw, int own_cap, int ro
     return PYRO_OK;
 }
 
+// The schedule of one Jacobian row (the reverse sweep with the cotangent on
+// one species): only the reactions in ``subset`` (those whose net
+// coefficient of that species is nonzero; every other reaction has a zero
+// cotangent), costliest first, packed into as few chunks of ``waves`` slots
+// as they fill (one reaction per wave per chunk), each chunk balanced over
+// the waves.  Species ownership is the given one (that of the full reverse
+// sweep, whose per-wave tables the row shares); a wave takes at most
+// ``pd_cap`` third-body and falloff reactions.
+int build_row_schedule(const SchedInput& in, const std::vector<int>& subset,
+                       const std::vector<std::vector<int>>& own, int waves, int row_bytes,
+                       int pd_cap, HostSched& out) {
+    const int S = in.S, R = in.R;
+    const auto& rtype = *in.rtype;
+    out.waves = waves;
+    out.rpw = 1;
+    out.own = own;
+    out.max_own = 0;
+    for (auto& o : out.own) out.max_own = std::max<int>(out.max_own, int(o.size()));
+    auto cost = [&](int j) {
+        double c = 1.0 + ((*in.rev)[j] ? 0.5 : 0.0);
+        if (rtype[j] >= 1) c += S / 24.0;
+        if (rtype[j] == 2) c += 1.5;
+        if (rtype[j] == 3) c += 6.0;
+        return c;
+    };
+    std::vector<int> order = subset;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost(a) > cost(b); });
+    out.n_chunks = int((order.size() + waves - 1) / waves);
+    out.recs.assign(size_t(std::max(out.n_chunks, 1)) * waves, RxnRec{});
+    for (auto& r : out.recs) {
+        std::memset(&r, 0, sizeof(r));
+        r.cls = kNoReaction;
+    }
+    out.slot_of.assign(R, -1);
+    out.chunk_of.assign(R, -1);
+    out.pd_of_wave.assign(waves, {});
+    for (int c = 0; c < out.n_chunks; ++c) {
+        std::vector<int> used(waves, 0);
+        for (size_t t = size_t(c) * waves; t < std::min(order.size(), size_t(c + 1) * waves); ++t) {
+            const int j = order[t];
+            const bool is_pd = rtype[j] >= 1;
+            int best = -1;
+            for (int w = 0; w < waves && best < 0; ++w)
+                if (!used[w] && !(is_pd && int(out.pd_of_wave[w].size()) >= pd_cap)) best = w;
+            if (best < 0) return fail(PYRO_E_UNSUPPORTED, "too many third-body reactions in a Jacobian row");
+            used[best] = 1;
+            if (is_pd) out.pd_of_wave[best].push_back(j);
+            out.slot_of[j] = best;
+            out.chunk_of[j] = c;
+            RxnRec& r = out.recs[size_t(c) * waves + best];
+            const auto& rj = (*in.reac)[j];
+            const auto& pj = (*in.prod)[j];
+            r.cls = rtype[j];
+            r.rev = (*in.rev)[j];
+            r.nr = int(rj.size());
+            r.np = int(pj.size());
+            for (int q = 0; q < kMaxSide; ++q) {
+                r.r[q] = q < r.nr ? rj[q] * row_bytes : 0;
+                r.p[q] = q < r.np ? pj[q] * row_bytes : 0;
+            }
+            r.dnu = (*in.dnu)[j];
+            r.prow = j;
+            r.pdw = is_pd ? int(out.pd_of_wave[best].size()) - 1 : -1;
+            r.fo = (*in.fo_idx)[j];
+            r.qoff = best * kTile * 8;
+            r.pd = (*in.pd_row)[j];
+        }
+    }
+    out.max_pdw = 0;
+    for (auto& p : out.pd_of_wave) out.max_pdw = std::max<int>(out.max_pdw, int(p.size()));
+    return PYRO_OK;
+}
+
 // Gathering lists of a schedule: per (chunk, wave), kMaxOwn + 1 boundaries
 // into the entries that entries(k, chunk, out) appends for owned species k.
 template <typename F>
@@ -584,6 +657,57 @@ int load_mechanism(const char* path, pyro_mech** out) {
         for (int j = 0; j < n_pd; ++j)
             for (size_t i = 0; i < bw.own[w].size() && i < size_t(own_stride); ++i)
                 veffo[(size_t(w) * n_pd + j) * own_stride + i] = f.eff[size_t(j) * S + bw.own[w][i]];
+    // the Jacobian rows' schedules and tables, concatenated over the rows;
+    // each row shares the reverse sweep's ownership tables (own, n_own,
+    // effo) and has its own records, gathering lists, efficiency queue and
+    // third-body list
+    struct RowOffsets { size_t rxn, gptr, gent, effw, n_pdw, pd_list; int n_chunks; };
+    std::vector<RowOffsets> row_off(S);
+    std::vector<RxnRec> jrecs;
+    std::vector<int32_t> jgptr, jn_pdw, jpd_list;
+    std::vector<uint32_t> jgent;
+    std::vector<double> jeffw;
+    for (int j = 0; j < S; ++j) {
+        std::vector<int> subset;
+        for (auto& e : by_species[j]) subset.push_back(e.first);
+        HostSched rs;
+        if (int rc = build_row_schedule(sin, subset, bw.own, kVjpWaves, kVjpRow, vpd_stride, rs)) {
+            delete m;
+            return rc;
+        }
+        RowOffsets& o = row_off[j];
+        o.n_chunks = rs.n_chunks;
+        o.rxn = jrecs.size();
+        jrecs.insert(jrecs.end(), rs.recs.begin(), rs.recs.end());
+        std::vector<int32_t> gp;
+        std::vector<uint32_t> ge;
+        gather_lists(rs, [&](int k, int c, std::vector<uint32_t>& out) {
+            for (auto& e : part[k])
+                if (rs.chunk_of[e[0]] == c) {
+                    out.push_back(uint32_t(rs.slot_of[e[0]] * kTile * 8) | (top16(double(e[1])) << 16));
+                    out.push_back(top16(-double(e[2])) | (top16(double(e[1] - e[2])) << 16));
+                }
+        }, gp, ge);
+        o.gptr = jgptr.size();
+        jgptr.insert(jgptr.end(), gp.begin(), gp.end());
+        o.gent = jgent.size();
+        jgent.insert(jgent.end(), ge.begin(), ge.end());
+        std::vector<double> ew;
+        std::vector<int32_t> np, ot, no;
+        wave_tables(rs, f.eff, pd_row, S, vpd_stride, ew, np, ot, no);
+        o.effw = jeffw.size();
+        jeffw.insert(jeffw.end(), ew.begin(), ew.end());
+        o.n_pdw = jn_pdw.size();
+        jn_pdw.insert(jn_pdw.end(), np.begin(), np.end());
+        o.pd_list = jpd_list.size();
+        for (int w = 0; w < kVjpWaves; ++w)
+            for (int i = 0; i < kMaxPd; ++i)
+                jpd_list.push_back(i < int(rs.pd_of_wave[w].size()) ? pd_row[rs.pd_of_wave[w][i]] : -1);
+    }
+    if (jrecs.empty()) jrecs.push_back(RxnRec{});
+    if (jgent.empty()) jgent.push_back(0u);
+    std::vector<DevSched> jrows(std::max(S, 1));   // device pointers filled after the allocation
+
     std::vector<double> params = m->params;
     if (params.empty()) params.push_back(0.0);
     // B fragments of eps^T for the MFMA third-body variant
@@ -694,6 +818,13 @@ int load_mechanism(const char* path, pyro_mech** out) {
         {veffo.data(), veffo.size() * sizeof(double), 0},
         {nu_frag.data(), nu_frag.size() * sizeof(double), 0},
         {lp_frag.data(), lp_frag.size() * sizeof(double), 0},
+        {jrecs.data(), jrecs.size() * sizeof(RxnRec), 0},
+        {jgptr.data(), jgptr.size() * sizeof(int32_t), 0},
+        {jgent.data(), jgent.size() * sizeof(uint32_t), 0},
+        {jeffw.data(), jeffw.size() * sizeof(double), 0},
+        {jn_pdw.data(), jn_pdw.size() * sizeof(int32_t), 0},
+        {jpd_list.data(), jpd_list.size() * sizeof(int32_t), 0},
+        {jrows.data(), jrows.size() * sizeof(DevSched), 0},
     };
     size_t total = 0;
     for (auto& p : parts) {
@@ -766,6 +897,28 @@ int load_mechanism(const char* path, pyro_mech** out) {
     d.nu_frag = reinterpret_cast<const double*>(base + parts[25].off);
     d.lp_frag = reinterpret_cast<const double*>(base + parts[26].off);
     d.lp_nks = lp_table ? lp_nks : 0;
+    // the Jacobian rows' schedule descriptors, now that the tables have
+    // device addresses, copied into their part of the allocation
+    for (int j = 0; j < S; ++j) {
+        const RowOffsets& o = row_off[j];
+        DevSched& r = jrows[j];
+        r = v;
+        r.n_chunks = o.n_chunks;
+        r.rxn = reinterpret_cast<const RxnRec*>(base + parts[27].off) + o.rxn;
+        r.gptr = reinterpret_cast<const int32_t*>(base + parts[28].off) + o.gptr;
+        r.gent = reinterpret_cast<const uint32_t*>(base + parts[29].off) + o.gent;
+        r.effw = reinterpret_cast<const double*>(base + parts[30].off) + o.effw;
+        r.n_pdw = reinterpret_cast<const int32_t*>(base + parts[31].off) + o.n_pdw;
+        r.pd_list = reinterpret_cast<const int32_t*>(base + parts[32].off) + o.pd_list;
+    }
+    err = hipMemcpy(static_cast<uint8_t*>(m->blob) + parts[33].off, jrows.data(), jrows.size() * sizeof(DevSched),
+                    hipMemcpyHostToDevice);
+    if (err != hipSuccess) {
+        (void)hipFree(m->blob);
+        delete m;
+        return hip_fail(err, "hipMemcpy of the Jacobian row schedules");
+    }
+    d.jac_rows = reinterpret_cast<const DevSched*>(base + parts[33].off);
     err = prepare_production_rates(m);
     if (err == hipSuccess) err = prepare_vjp(m);
     if (err != hipSuccess) {

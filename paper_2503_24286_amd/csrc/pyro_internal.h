@@ -175,6 +175,10 @@ struct DevMech {
     // [lane] = nu[4 kk + l/16][slot 16 sb + l%16] (zero for empty slots and
     // species past S); lp_nks K-steps of 4 species (0: table not built)
     const double* lp_frag;
+    // Jacobian rows: per species j, the reverse-sweep schedule of the
+    // reactions with a nonzero net coefficient of j ([S]; ownership tables
+    // shared with vjp)
+    const DevSched* jac_rows;
     // surrogate
     int32_t E;                           // elements
     int32_t lp_nks;
