@@ -477,13 +477,9 @@ __global__ __launch_bounds__(kVjpWaves * 64) void vjp_kernel(
         }
 
         // ---- Mbar of this wave's third-body reactions into LDS, once every
-        // wave is done with the chunk buffers (Jacobian rows: the rows of
-        // third-body reactions outside the row's schedule are zero)
+        // wave is done with the chunk buffers (a Jacobian row writes and
+        // later reads only its own third-body rows)
         __syncthreads();
-        if constexpr (JAC != 0) {
-            for (int i = threadIdx.x; i < m.n_pd * kTile; i += kVjpWaves * 64) mbar[i] = 0.0;
-            __syncthreads();
-        }
         {
             const cptr<int32_t> pl = cst(sc.pd_list) + w * kMaxPd;
 #pragma unroll
@@ -497,7 +493,17 @@ __global__ __launch_bounds__(kVjpWaves * 64) void vjp_kernel(
         double cmv[MAXOWN];
 #pragma unroll
         for (int i = 0; i < MAXOWN; ++i) cmv[i] = 0.0;
-        {
+        if constexpr (JAC != 0) {
+            // a Jacobian row: only its own third-body rows have M-bar
+            const cptr<double> eo = cst(sc.effo) + size_t(w) * m.n_pd * MAXOWN;
+            const cptr<int32_t> pr = cst(sc.pd_rows);
+            for (int t = 0; t < sc.n_pd_rows; ++t) {
+                const int j = pr[t];
+                const double mb = mbar[size_t(j) * kTile + lane];
+#pragma unroll
+                for (int i = 0; i < MAXOWN; ++i) cmv[i] = fma(eo[j * MAXOWN + i], mb, cmv[i]);
+            }
+        } else {
             const cptr<double> eo = cst(sc.effo) + size_t(w) * m.n_pd * MAXOWN;
             int j = 0;
             for (; j + 4 <= m.n_pd; j += 4) {

@@ -661,10 +661,10 @@ int load_mechanism(const char* path, pyro_mech** out) {
     // each row shares the reverse sweep's ownership tables (own, n_own,
     // effo) and has its own records, gathering lists, efficiency queue and
     // third-body list
-    struct RowOffsets { size_t rxn, gptr, gent, effw, n_pdw, pd_list; int n_chunks; };
+    struct RowOffsets { size_t rxn, gptr, gent, effw, n_pdw, pd_list, pd_rows; int n_chunks, n_pd_rows; };
     std::vector<RowOffsets> row_off(S);
     std::vector<RxnRec> jrecs;
-    std::vector<int32_t> jgptr, jn_pdw, jpd_list;
+    std::vector<int32_t> jgptr, jn_pdw, jpd_list, jpd_rows;
     std::vector<uint32_t> jgent;
     std::vector<double> jeffw;
     for (int j = 0; j < S; ++j) {
@@ -703,7 +703,16 @@ int load_mechanism(const char* path, pyro_mech** out) {
         for (int w = 0; w < kVjpWaves; ++w)
             for (int i = 0; i < kMaxPd; ++i)
                 jpd_list.push_back(i < int(rs.pd_of_wave[w].size()) ? pd_row[rs.pd_of_wave[w][i]] : -1);
+        // the row's third-body rows, ascending (the rows whose M-bar it stages)
+        o.pd_rows = jpd_rows.size();
+        std::vector<int> rows;
+        for (int w = 0; w < kVjpWaves; ++w)
+            for (int jr : rs.pd_of_wave[w]) rows.push_back(pd_row[jr]);
+        std::sort(rows.begin(), rows.end());
+        o.n_pd_rows = int(rows.size());
+        jpd_rows.insert(jpd_rows.end(), rows.begin(), rows.end());
     }
+    if (jpd_rows.empty()) jpd_rows.push_back(0);
     if (jrecs.empty()) jrecs.push_back(RxnRec{});
     if (jgent.empty()) jgent.push_back(0u);
     std::vector<DevSched> jrows(std::max(S, 1));   // device pointers filled after the allocation
@@ -825,6 +834,7 @@ int load_mechanism(const char* path, pyro_mech** out) {
         {jn_pdw.data(), jn_pdw.size() * sizeof(int32_t), 0},
         {jpd_list.data(), jpd_list.size() * sizeof(int32_t), 0},
         {jrows.data(), jrows.size() * sizeof(DevSched), 0},
+        {jpd_rows.data(), jpd_rows.size() * sizeof(int32_t), 0},
     };
     size_t total = 0;
     for (auto& p : parts) {
@@ -910,6 +920,8 @@ int load_mechanism(const char* path, pyro_mech** out) {
         r.effw = reinterpret_cast<const double*>(base + parts[30].off) + o.effw;
         r.n_pdw = reinterpret_cast<const int32_t*>(base + parts[31].off) + o.n_pdw;
         r.pd_list = reinterpret_cast<const int32_t*>(base + parts[32].off) + o.pd_list;
+        r.n_pd_rows = o.n_pd_rows;
+        r.pd_rows = reinterpret_cast<const int32_t*>(base + parts[34].off) + o.pd_rows;
     }
     err = hipMemcpy(static_cast<uint8_t*>(m->blob) + parts[33].off, jrows.data(), jrows.size() * sizeof(DevSched),
                     hipMemcpyHostToDevice);

@@ -123,7 +123,7 @@ __device__ inline double from_top16(uint32_t top) {
 // reaction slots, species owned per wave, gathering lists.
 struct DevSched {
     int32_t n_chunks;
-    int32_t pad;
+    int32_t n_pd_rows;                   // Jacobian rows: third-body rows of the row
     const RxnRec* rxn;                   // [n_chunks][waves][rpw]
     const double* effw;                  // [waves][S][MAXPD] efficiencies by queue slot
     const int32_t* n_pdw;                // [waves]
@@ -136,6 +136,7 @@ struct DevSched {
     const uint32_t* gent;
     const int32_t* pd_list;              // [waves][kMaxPd] third-body rows in chunk order
     const double* effo;                  // [waves][n_pd][MAXOWN] by owned species
+    const int32_t* pd_rows;              // Jacobian rows: [n_pd_rows] third-body rows
 };
 
 struct DevMech {
