@@ -266,8 +266,8 @@ def jacobian_leg(args, log):
     return {"workload": f"53-species mechanism, {n} cells, fixed density and internal energy",
             "ms": round(ms, 3), "Mcells_s": round(n / (ms * 1e-3) / 1e6, 3), "finite": ok,
             "hbm_GBps_compulsory": round(out_bytes * n / (ms * 1e-3) / 1e9, 1),
-            "method": "S reverse sweeps, unit cotangent W_j on species j per row; reactions "
-                      "without species j skipped"}
+            "method": "S reverse sweeps, unit cotangent W_j on species j per row, each row on "
+                      "a schedule of its own reactions (nonzero net coefficient of j)"}
 
 
 def large_mechanism_leg(args, log):
