@@ -270,6 +270,84 @@ def jacobian_leg(args, log):
                       "a schedule of its own reactions (nonzero net coefficient of j)"}
 
 
+def other_rows_leg(args, log):
+    """The remaining per-cell kernels on the 53-species workload: Newton
+    inversion from the enthalpy and primitive variables from conserved ones
+    (2^22 cells, HBM-bound: algorithmic bytes = inputs read + outputs
+    written), mixture-averaged transport (2^20 cells, ALU-bound: about 2 S^2
+    pair updates per cell) and one reactor step, RK4 (2^20 cells) and
+    Crank-Nicolson with Newton on the fixed-energy Jacobian (2^18 cells)."""
+    import numpy as np
+    import torch
+
+    import paper_2503_24286_amd as pyro
+    from pyro_synth.states import draw_states
+    from pyro_synth.transport import draw_transport
+    gm = pyro.Mechanism(MECH)
+    S = gm.n_species
+    stream = torch.cuda.current_stream()
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
+    out = {}
+    n = args.cells
+    T, p, Y = (dev(x) for x in draw_states(1, n, S))
+    rho = pyro.density(gm, p, T, Y)
+    e = pyro.internal_energy(gm, T, Y)
+    h = e + p / rho
+    reps = max(args.steps, 3)
+    ms = _time_ms(lambda: pyro.temperature_from_enthalpy(gm, h, Y), reps, stream)
+    b = 8 * (1 + S) + 8 + 4
+    out["temperature_from_enthalpy"] = {
+        "cells": n, "ms": round(ms, 4), "Mcells_s": round(n / (ms * 1e-3) / 1e6, 1),
+        "bytes_per_cell": b, "hbm_GBps": round(b * n / (ms * 1e-3) / 1e9, 1),
+        "roofline": {"bound": "hbm", "peak": 8000.0, "unit": "GB/s",
+                     "frac": round(b * n / (ms * 1e-3) / 8e12, 3)}}
+    rk = rho * Y
+    mom = torch.randn((3, Y.stride(0)), dtype=torch.float64, device="cuda")[:, :n] * rho
+    E = rho * e + 0.5 * (mom * mom).sum(0) / rho
+    ms = _time_ms(lambda: pyro.primitive_from_conserved(gm, rk, mom, E), reps, stream)
+    b = 8 * (S + 3 + 1) + 8 * (1 + S + 3 + 2) + 4
+    out["primitive_from_conserved"] = {
+        "cells": n, "dim": 3, "ms": round(ms, 4), "Mcells_s": round(n / (ms * 1e-3) / 1e6, 1),
+        "bytes_per_cell": b, "hbm_GBps": round(b * n / (ms * 1e-3) / 1e9, 1),
+        "roofline": {"bound": "hbm", "peak": 8000.0, "unit": "GB/s",
+                     "frac": round(b * n / (ms * 1e-3) / 8e12, 3)}}
+    del rk, mom, E, h
+    n2 = 1 << 20
+    T2, Y2, rho2, e2 = T[:n2].clone(), Y[:, :n2].contiguous(), rho[:n2].clone(), e[:n2].clone()
+    del T, p, Y, rho, e
+    tr = pyro.Transport(gm, *draw_transport(S))
+    ms = _time_ms(lambda: pyro.mixture_transport(gm, tr, T2, Y2), reps, stream)
+    out["mixture_transport"] = {"cells": n2, "ms": round(ms, 4),
+                                "Mcells_s": round(n2 / (ms * 1e-3) / 1e6, 1),
+                                "pair_updates_per_cell": 2 * S * S}
+    dt = 1e-8
+    Ys, Ts = Y2.clone(), T2.clone()
+    ms = _time_ms(lambda: (Ys.copy_(Y2), Ts.copy_(T2),
+                           pyro.reactor_step(gm, "rk4", rho2, e2, Ys, Ts, dt)), 3, stream)
+    out["reactor_rk4_step"] = {"cells": n2, "dt_s": dt, "ms": round(ms, 3),
+                               "Mcells_s": round(n2 / (ms * 1e-3) / 1e6, 2),
+                               "note": "four stages of Newton T(e), production rates and the "
+                                       "stage update; includes restoring the state per step"}
+    n3 = 1 << 18
+    Y3, T3, r3, e3 = (Y2[:, :n3].contiguous(), T2[:n3].clone(), rho2[:n3].clone(),
+                      e2[:n3].clone())
+    Yc, Tc = Y3.clone(), T3.clone()
+    st = pyro.reactor_step(gm, "cn", r3, e3, Yc, Tc, dt)
+    iters = st.cpu().numpy()
+    ms = _time_ms(lambda: (Yc.copy_(Y3), Tc.copy_(T3),
+                           pyro.reactor_step(gm, "cn", r3, e3, Yc, Tc, dt)), 3, stream)
+    out["reactor_cn_step"] = {"cells": n3, "dt_s": dt, "ms": round(ms, 3),
+                              "Mcells_s": round(n3 / (ms * 1e-3) / 1e6, 3),
+                              "newton_updates_max": int(np.abs(iters).max()),
+                              "converged_fraction": float((iters >= 0).mean()),
+                              "note": "per Newton update: T, production rates, the 53-row "
+                                      "fixed-energy Jacobian and a batched LU solve"}
+    gm.close()
+    torch.cuda.empty_cache()
+    log("other rows: " + ", ".join(f"{k} {v['ms']} ms" for k, v in out.items()))
+    return out
+
+
 def large_mechanism_leg(args, log):
     """The 160-species, 900-reaction mechanism (2^20 cells, states drawn as
     for the 53-species workload): production rates alone, with the kernel
@@ -462,6 +540,8 @@ def main():
                          "1/64 of them)")
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--no-jacobian", action="store_true")
+    ap.add_argument("--no-other-rows", action="store_true",
+                    help="skip the enthalpy, primitive-variable, transport and reactor legs")
     ap.add_argument("--jacobian-cells", type=int, default=1 << 18)
     ap.add_argument("--no-large", action="store_true",
                     help="skip the 160-species mechanism's production-rate line")
@@ -630,6 +710,8 @@ def main():
         print(f"# {msg}", file=sys.stderr, flush=True)
     if not args.no_jacobian:
         result["jacobian"] = jacobian_leg(args, log)
+    if not args.no_other_rows:
+        result["other_rows"] = other_rows_leg(args, log)
     if not args.no_large:
         result["large_mechanism"] = large_mechanism_leg(args, log)
     if not args.no_surrogate:
