@@ -294,7 +294,8 @@ __global__ __launch_bounds__(kVjpWaves * 64) void vjp_kernel(
     const double* __restrict__ T, const double* __restrict__ Y,
     const double* __restrict__ wbar, double* __restrict__ Ybar, double* __restrict__ Tbar,
     double* __restrict__ wdot, double* __restrict__ partial, const double* __restrict__ params,
-    int unit = -1, const double* __restrict__ lnTg = nullptr) {
+    int unit = -1, const double* __restrict__ lnTg = nullptr, int64_t out_ld = 0,
+    int64_t out_tile = 0) {
     static_assert(JAC == 0 || !WITH_W, "Jacobian rows do not return omega");
     constexpr int kBuf = (WITH_W ? 3 : 2) * kPlane;   // one chunk buffer: a, b (, q) planes
     extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
@@ -323,6 +324,11 @@ __global__ __launch_bounds__(kVjpWaves * 64) void vjp_kernel(
     for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
         const int64_t cell = tile * kTile + lane;
         const bool valid = cell < n;
+        // Jacobian rows: element k of this cell's row at Ybar[k out_ld + ocell]
+        // (out_ld = ld, out_tile = 64: the species-major layout; out_ld = 64,
+        // out_tile = S S 64: 64-cell tiles of whole matrices)
+        const int64_t ocell = JAC ? tile * out_tile + lane : cell;
+        const int64_t old = JAC ? out_ld : ld;
         const int64_t c = valid ? cell : n - 1;
         CellState cs;
         cs.T = T[c];
@@ -545,7 +551,7 @@ __global__ __launch_bounds__(kVjpWaves * 64) void vjp_kernel(
                     ybs[i] = ybar;
                     eks[i] = kGasConstant * cs.T * (hRT - 1.0) * sp.inv_w;
                 } else if (valid) {
-                    Ybar[size_t(k) * ld + cell] = ybar;
+                    Ybar[size_t(k) * old + ocell] = ybar;
                     if (WITH_W) wdot[size_t(k) * ld + cell] = ws[i];
                 }
             }
@@ -565,7 +571,7 @@ __global__ __launch_bounds__(kVjpWaves * 64) void vjp_kernel(
             const double g = st / cv;
 #pragma unroll
             for (int i = 0; i < MAXOWN; ++i)
-                if (i < nown && valid) Ybar[size_t(own[i]) * ld + cell] = fma(-g, eks[i], ybs[i]);
+                if (i < nown && valid) Ybar[size_t(own[i]) * old + ocell] = fma(-g, eks[i], ybs[i]);
             if (w == 0 && valid && Tbar) Tbar[cell] = st;
         } else if (w == 0) {
             double s = 0.0;
@@ -663,15 +669,18 @@ hipError_t set_lds_own(int bytes) {
 template <int MAXOWN, int MAXPD, int JAC>
 hipError_t launch_jacobian_rows(const pyro_mech* m, int64_t n, int64_t ld, const double* rho,
                                 const double* T, const double* Y, double* J, double* dSdT,
-                                const double* params, hipStream_t stream) {
+                                const double* params, bool tiled, hipStream_t stream) {
     const int64_t n_tiles = (n + kTile - 1) / kTile;
     const int blocks = int(std::min<int64_t>(n_tiles, int64_t(m->n_cu)));
     const size_t lds = vjp_lds_bytes(m);
+    const int64_t S = m->S;
+    const int64_t out_ld = tiled ? kTile : ld, out_tile = tiled ? S * S * kTile : kTile;
     for (int j = 0; j < m->S; ++j) {
         hipLaunchKernelGGL((vjp_kernel<MAXOWN, MAXPD, false, JAC>), dim3(unsigned(blocks)),
                            dim3(kVjpWaves * 64), lds, stream, m->dev, n, ld, rho, T, Y,
-                           nullptr, J + size_t(j) * m->S * ld,
-                           dSdT ? dSdT + size_t(j) * ld : nullptr, nullptr, nullptr, params, j);
+                           nullptr, J + size_t(j) * S * out_ld,
+                           dSdT ? dSdT + size_t(j) * ld : nullptr, nullptr, nullptr, params, j,
+                           nullptr, out_ld, out_tile);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -681,23 +690,26 @@ hipError_t launch_jacobian_rows(const pyro_mech* m, int64_t n, int64_t ld, const
 template <int MAXOWN, int JAC>
 hipError_t launch_jacobian_own(const pyro_mech* m, int64_t n, int64_t ld, const double* rho,
                                const double* T, const double* Y, double* J, double* dSdT,
-                               const double* params, hipStream_t stream) {
+                               const double* params, bool tiled, hipStream_t stream) {
     if (m->vjp_max_pdw <= 4)
-        return launch_jacobian_rows<MAXOWN, 4, JAC>(m, n, ld, rho, T, Y, J, dSdT, params, stream);
+        return launch_jacobian_rows<MAXOWN, 4, JAC>(m, n, ld, rho, T, Y, J, dSdT, params, tiled,
+                                                    stream);
     if (m->vjp_max_pdw <= 8)
-        return launch_jacobian_rows<MAXOWN, 8, JAC>(m, n, ld, rho, T, Y, J, dSdT, params, stream);
-    return launch_jacobian_rows<MAXOWN, 16, JAC>(m, n, ld, rho, T, Y, J, dSdT, params, stream);
+        return launch_jacobian_rows<MAXOWN, 8, JAC>(m, n, ld, rho, T, Y, J, dSdT, params, tiled,
+                                                    stream);
+    return launch_jacobian_rows<MAXOWN, 16, JAC>(m, n, ld, rho, T, Y, J, dSdT, params, tiled,
+                                                 stream);
 }
 
 template <int JAC>
 hipError_t launch_jacobian_mode(const pyro_mech* m, int64_t n, int64_t ld, const double* rho,
                                 const double* T, const double* Y, double* J, double* dSdT,
-                                const double* params, hipStream_t stream) {
+                                const double* params, bool tiled, hipStream_t stream) {
     if (m->vjp_max_own <= 4)
-        return launch_jacobian_own<4, JAC>(m, n, ld, rho, T, Y, J, dSdT, params, stream);
+        return launch_jacobian_own<4, JAC>(m, n, ld, rho, T, Y, J, dSdT, params, tiled, stream);
     if (m->vjp_max_own <= 8)
-        return launch_jacobian_own<8, JAC>(m, n, ld, rho, T, Y, J, dSdT, params, stream);
-    return launch_jacobian_own<16, JAC>(m, n, ld, rho, T, Y, J, dSdT, params, stream);
+        return launch_jacobian_own<8, JAC>(m, n, ld, rho, T, Y, J, dSdT, params, tiled, stream);
+    return launch_jacobian_own<16, JAC>(m, n, ld, rho, T, Y, J, dSdT, params, tiled, stream);
 }
 
 // zeroes n doubles (a kernel rather than a memset node, for callers that
@@ -794,8 +806,14 @@ hipError_t launch_chemical_jacobian(const pyro_mech* m, int64_t n, int64_t ld, c
                                     hipStream_t stream) {
     const double* p = params ? params : m->dev.params;
     if (fixed_energy)
-        return launch_jacobian_mode<2>(m, n, ld, rho, T, Y, J, dSdT, p, stream);
-    return launch_jacobian_mode<1>(m, n, ld, rho, T, Y, J, dSdT, p, stream);
+        return launch_jacobian_mode<2>(m, n, ld, rho, T, Y, J, dSdT, p, false, stream);
+    return launch_jacobian_mode<1>(m, n, ld, rho, T, Y, J, dSdT, p, false, stream);
+}
+
+hipError_t launch_chemical_jacobian_tiled(const pyro_mech* m, int64_t n, int64_t ld,
+                                          const double* rho, const double* T, const double* Y,
+                                          double* J, hipStream_t stream) {
+    return launch_jacobian_mode<2>(m, n, ld, rho, T, Y, J, nullptr, m->dev.params, true, stream);
 }
 
 size_t vjp_lds_bytes(const pyro_mech* m) {

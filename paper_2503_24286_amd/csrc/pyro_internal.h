@@ -282,6 +282,12 @@ hipError_t launch_chemical_jacobian(const pyro_mech* m, int64_t n, int64_t ld, c
                                     const double* T, const double* Y, int fixed_energy,
                                     double* J, double* dSdT, const double* params,
                                     hipStream_t stream);
+// The same at fixed energy, J in 64-cell tiles of whole matrices: element
+// (j, k) of cell c at J[((c / 64) S S + j S + k) 64 + c % 64], so that one
+// cell's matrix spans one tile (S S 64 doubles) rather than S S cell rows.
+hipError_t launch_chemical_jacobian_tiled(const pyro_mech* m, int64_t n, int64_t ld,
+                                          const double* rho, const double* T, const double* Y,
+                                          double* J, hipStream_t stream);
 size_t vjp_lds_bytes(const pyro_mech* m);
 // Fixed scratch of the allocation-free VJP (per-workgroup parameter partials).
 constexpr size_t kVjpScratchDoubles = size_t(1) << 19;    // 4 MiB

@@ -7,7 +7,7 @@ import pytest
 
 import mechs
 from gpu_util import announce, record, states, to_dev, torch_cuda
-from oracle import kinetics, reactor, thermo
+from oracle import eos, kinetics, reactor, thermo
 
 pytestmark = pytest.mark.gpu
 
@@ -76,6 +76,58 @@ def test_cn_step_matches_oracle(lib_mechs, cfg, n):
     record(f"reactor cn cfg{cfg} n={n}", "Y scaled", eY, 1e-12)
     record(f"reactor cn cfg{cfg} n={n}", "T relative", eT, 1e-12)
     np.testing.assert_allclose(Yg.sum(axis=0), Y.sum(axis=0), rtol=1e-13)
+    assert eY <= 1e-12 and eT <= 1e-12
+
+
+def test_cn_step_past_64_species(tmp_path):
+    """66 species (the solve's one-cell-per-lane form, past the 64 of the
+    one-cell-per-wavefront form): 33 isomer pairs A_i <-> B_i and the
+    bimolecular exchanges A_i + A_i+1 <-> B_i + B_i+1, constant heat
+    capacities, a Crank-Nicolson step of one chemical time scale against the
+    oracle's; the cells converge at different updates, so the later updates
+    run on the gathered remaining cells."""
+    torch = torch_cuda()
+    import paper_2503_24286_amd as pyro
+    rng = np.random.default_rng(66)
+    H, S = 33, 66
+    Wh = rng.uniform(0.002, 0.05, H)
+    a1 = rng.uniform(2.5, 4.5, S)
+    a6 = rng.uniform(-3e4, 3e4, S)
+    rx = []
+    for i in range(H):
+        rx.append(dict(reac=[(i, 1)], prod=[(H + i, 1)],
+                       arrh=(np.log(rng.uniform(1e6, 1e8)), rng.uniform(-0.5, 0.5),
+                             rng.uniform(1e5, 2e5))))
+    for i in range(H - 1):
+        rx.append(dict(reac=[(i, 1), (i + 1, 1)], prod=[(H + i, 1), (H + i + 1, 1)],
+                       arrh=(np.log(rng.uniform(1e6, 1e8)), rng.uniform(-0.5, 0.5),
+                             rng.uniform(1e5, 2e5))))
+    path = str(tmp_path / "pairs.pyromech")
+    m = mechs.make(path, W=np.concatenate([Wh, Wh]), nasa_low=mechs.constant_cp(S, a1, a6, 10.0),
+                   reactions=rx)
+    n = 96
+    T = rng.uniform(1000.0, 1800.0, n)
+    Y = rng.uniform(0.0, 1.0, (S, n)) ** 4
+    Y /= Y.sum(axis=0)
+    rho = eos.density(m, np.full(n, 101325.0), T, Y)
+    e = thermo.mixture_internal_energy(m, T, Y)
+    f, _ = reactor.rhs(m, rho, e, Y, T)
+    with np.errstate(divide="ignore"):
+        dt = np.min(np.where(np.abs(f) > 0, np.maximum(Y, 1e-3) / np.abs(f), np.inf), axis=0)
+    gm = pyro.Mechanism(path)
+    try:
+        announce(f"reactor cn 66 species n={n}")
+        Yg, Tg, st = _gpu_step(torch, pyro, gm, "cn", rho, e, Y, T, dt)
+    finally:
+        gm.close()
+    Yr, Tr, st_r = reactor.cn_step(m, rho, e, Y, T, dt)
+    assert np.all(st > 0) and np.all(st_r > 0)
+    assert np.all(np.abs(st - st_r) <= 1)
+    assert len(np.unique(st_r)) > 1
+    eY = np.max(np.abs(Yg - Yr) / _scale(m, rho, T, Y, dt))
+    eT = np.max(np.abs(Tg - Tr) / Tr)
+    record(f"reactor cn 66 species n={n}", "Y scaled", eY, 1e-12)
+    record(f"reactor cn 66 species n={n}", "T relative", eT, 1e-12)
     assert eY <= 1e-12 and eT <= 1e-12
 
 
