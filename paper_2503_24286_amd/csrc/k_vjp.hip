@@ -529,7 +529,6 @@ __global__ __launch_bounds__(kVjpWaves * 64) void vjp_kernel(
             }
         }
         // ---- species results
-        double ybs[JAC == 2 ? MAXOWN : 1], eks[JAC == 2 ? MAXOWN : 1];
 #pragma unroll
         for (int i = 0; i < MAXOWN; ++i) {
             if (i < nown) {
@@ -546,11 +545,10 @@ __global__ __launch_bounds__(kVjpWaves * 64) void vjp_kernel(
                 const double h_hi = enthalpy_poly(ns.hi, cs.T, cs.invT);
                 const double hRT = cs.T <= sp.t_mid ? h_lo : h_hi;
                 tbar -= gam[i] * hRT * cs.invT;
-                if constexpr (JAC == 2) {
-                    // held until dS/dT is known: e_k = (h_k - R T)/W_k (eq. int_energy)
-                    ybs[i] = ybar;
-                    eks[i] = kGasConstant * cs.T * (hRT - 1.0) * sp.inv_w;
-                } else if (valid) {
+                // (fixed energy: completed below, once dS/dT is known; the
+                // partial row goes to memory rather than being held in
+                // registers across the sums)
+                if (valid) {
                     Ybar[size_t(k) * old + ocell] = ybar;
                     if (WITH_W) wdot[size_t(k) * ld + cell] = ws[i];
                 }
@@ -570,8 +568,20 @@ __global__ __launch_bounds__(kVjpWaves * 64) void vjp_kernel(
             }
             const double g = st / cv;
 #pragma unroll
-            for (int i = 0; i < MAXOWN; ++i)
-                if (i < nown && valid) Ybar[size_t(own[i]) * old + ocell] = fma(-g, eks[i], ybs[i]);
+            for (int i = 0; i < MAXOWN; ++i) {
+                if (i < nown && valid) {
+                    // e_k = (h_k - R T)/W_k (eq. int_energy), formed again
+                    const int k = own[i];
+                    const SpeciesRec sp = cst(m.species)[k];
+                    const NewtonSpecies ns = cst(m.newton)[k];
+                    const double h_lo = enthalpy_poly(ns.lo, cs.T, cs.invT);
+                    const double h_hi = enthalpy_poly(ns.hi, cs.T, cs.invT);
+                    const double hRT = cs.T <= sp.t_mid ? h_lo : h_hi;
+                    const double ek = kGasConstant * cs.T * (hRT - 1.0) * sp.inv_w;
+                    double* o = Ybar + size_t(k) * old + ocell;
+                    *o = fma(-g, ek, *o);
+                }
+            }
             if (w == 0 && valid && Tbar) Tbar[cell] = st;
         } else if (w == 0) {
             double s = 0.0;
