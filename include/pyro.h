@@ -353,11 +353,14 @@ PYRO_API int pyro_mixture_transport(const pyro_mech* mech, const pyro_transport*
  *                     (eq. crank_nicol_rhs with the density of eq. massfrac_ode)
  *                     solved by Newton with the matrix I - dt/(2 rho) J
  *                     (eq. crank_nicol_jac; J = dS/dY at fixed density and
- *                     energy, as pyro_chemical_jacobian) from Y^m, until the
- *                     first update with max_k |dY_k| <= tol or max_newton
- *                     updates; each update solves every cell's S x S system
- *                     by Gaussian elimination with partial pivoting.  The
- *                     call waits on the stream after each update to stop once
+ *                     energy, as pyro_chemical_jacobian) from Y^m, per cell
+ *                     until the first update with every |dY_k| <= tol (an
+ *                     update holding a NaN never qualifies) or max_newton
+ *                     updates; each update solves the S x S system of every
+ *                     cell still iterating with partial pivoting
+ *                     (Gauss-Jordan, one cell per wavefront, up to 64
+ *                     species; Gaussian elimination past that).  The call
+ *                     waits on the stream after each update to stop once
  *                     every cell has converged.
  *
  *   rho[n], e[n]      density and internal energy (constant over the step)
