@@ -21,6 +21,8 @@
 //    costs a translation miss per element at 2^18 cells), and once some cells
 //    have converged, the Jacobian and the solve run on the others only,
 //    gathered in ascending order.
+#include <type_traits>
+
 #include "pyro_internal.h"
 #include "surrogate_internal.h"
 
@@ -153,36 +155,30 @@ __global__ __launch_bounds__(kRBlock) void cn_solve_kernel(
 
 constexpr int kWBlock = 512;   // eight cells per workgroup
 
-// one DPP move of a double within rows of 16 lanes
-template <int CTRL>
-__device__ inline double row_dpp(double v) {
-    const int2 h = __builtin_bit_cast(int2, v);
-    int2 r;
-    r.x = __builtin_amdgcn_mov_dpp(h.x, CTRL, 0xf, 0xf, false);
-    r.y = __builtin_amdgcn_mov_dpp(h.y, CTRL, 0xf, 0xf, false);
-    return __builtin_bit_cast(double, r);
-}
-
-// the larger of v and its partner l ^ 16 (SWAP16) or l ^ 32: with both
-// operands equal to v, the swap returns v and the partner in some order
-template <bool SWAP16>
-__device__ inline double max_swap(double v) {
-    const int2 h = __builtin_bit_cast(int2, v);
-    const auto lo = SWAP16 ? __builtin_amdgcn_permlane16_swap(h.x, h.x, false, false)
-                           : __builtin_amdgcn_permlane32_swap(h.x, h.x, false, false);
-    const auto hi = SWAP16 ? __builtin_amdgcn_permlane16_swap(h.y, h.y, false, false)
-                           : __builtin_amdgcn_permlane32_swap(h.y, h.y, false, false);
-    return fmax(__builtin_bit_cast(double, int2{int(lo[0]), int(hi[0])}),
-                __builtin_bit_cast(double, int2{int(lo[1]), int(hi[1])}));
-}
-
 // the maximum over the 64 lanes, in every lane (NaN lanes ignored)
-__device__ inline double wave_max(double x) {
-    x = fmax(x, row_dpp<0x121>(x));   // row_ror:1
-    x = fmax(x, row_dpp<0x122>(x));   // row_ror:2
-    x = fmax(x, row_dpp<0x124>(x));   // row_ror:4
-    x = fmax(x, row_dpp<0x128>(x));   // row_ror:8
-    return max_swap<false>(max_swap<true>(x));
+__device__ inline float wave_max(float x) {
+    auto dpp = [](float v, auto ctrl) {
+        return __builtin_bit_cast(
+            float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), decltype(ctrl)::value,
+                                            0xf, 0xf, false));
+    };
+    x = fmaxf(x, dpp(x, std::integral_constant<int, 0x121>{}));   // row_ror:1
+    x = fmaxf(x, dpp(x, std::integral_constant<int, 0x122>{}));   // row_ror:2
+    x = fmaxf(x, dpp(x, std::integral_constant<int, 0x124>{}));   // row_ror:4
+    x = fmaxf(x, dpp(x, std::integral_constant<int, 0x128>{}));   // row_ror:8
+    const int b = __builtin_bit_cast(int, x);
+    const auto s16 = __builtin_amdgcn_permlane16_swap(b, b, false, false);
+    x = fmaxf(__builtin_bit_cast(float, int(s16[0])), __builtin_bit_cast(float, int(s16[1])));
+    const int c = __builtin_bit_cast(int, x);
+    const auto s32 = __builtin_amdgcn_permlane32_swap(c, c, false, false);
+    return fmaxf(__builtin_bit_cast(float, int(s32[0])), __builtin_bit_cast(float, int(s32[1])));
+}
+
+// 1/d to within an ulp or so: the hardware estimate and two Newton steps
+__device__ inline double recip(double d) {
+    double r = __builtin_amdgcn_rcp(d);
+    r = fma(r, fma(-d, r, 1.0), r);
+    return fma(r, fma(-d, r, 1.0), r);
 }
 
 __device__ inline double read_lane(double v, int l) {
@@ -258,8 +254,11 @@ __global__ __launch_bounds__(kWBlock) __attribute__((amdgpu_waves_per_eu(3))) vo
         for (int u = 0; u < 8; ++u) {
             const int col = 8 * t + u;
             if (col >= S) break;
-            const double key = done ? -1.0 : fabs(a[0]);
-            const double best = wave_max(key);
+            // the pivot: the largest |a| of the rows not yet pivots, compared
+            // in single precision (a row within a float rounding of the
+            // largest serves as well)
+            const float key = done ? -1.0f : float(fabs(a[0]));
+            const float best = wave_max(key);
             uint64_t hit = __ballot(!done && key == best);
             if (hit == 0) hit = __ballot(!done);   // a column of NaN
             const int p = first_lane(hit);
@@ -270,7 +269,7 @@ __global__ __launch_bounds__(kWBlock) __attribute__((amdgpu_waves_per_eu(3))) vo
                 mycol = col;
                 diag = d;
             }
-            const double l = me ? 0.0 : a[0] * (1.0 / d);
+            const double l = me ? 0.0 : a[0] * recip(d);
 #pragma unroll
             for (int q = 1; q < NC - 8 * t; ++q) a[q - 1] = fma(-l, read_lane(a[q], p), a[q]);
             a[NC - 8 * t - 1] = 0.0;
