@@ -110,6 +110,30 @@ def test_cn_step_sampled_at_scale(lib_mechs):
     assert eY <= 1e-12 and eT <= 1e-12
 
 
+def test_cn_step_padded_rows(lib_mechs):
+    """Species rows of stride ld > n (the Newton updates gather from and
+    write back to the padded layout): 40 config-1 cells in rows of 64; the
+    padding is left untouched."""
+    torch, pyro, gms = lib_mechs
+    m = mechs.load_config(1)
+    n, ld = 40, 64
+    T, Y, rho, e, dt = _setup(m, 1, n, 500, 1.0)
+    announce(f"reactor cn cfg1 n={n} ld={ld}")
+    Yp = torch.full((m.S, ld), 7.0, dtype=torch.float64, device="cuda")
+    Yp[:, :n] = torch.from_numpy(Y).cuda()
+    r, ee, t, h = to_dev(torch, rho, e, T, dt)
+    st = pyro.reactor_step(gms[1], "cn", r, ee, Yp[:, :n], t, h).cpu().numpy()
+    Yg, Tg = Yp.cpu().numpy(), t.cpu().numpy()
+    Yr, Tr, st_r = reactor.cn_step(m, rho, e, Y, T, dt)
+    assert np.all(Yg[:, n:] == 7.0)
+    assert np.all(st > 0) and np.all(np.abs(st - st_r) <= 1)
+    eY = np.max(np.abs(Yg[:, :n] - Yr) / _scale(m, rho, T, Y, dt))
+    eT = np.max(np.abs(Tg - Tr) / Tr)
+    record(f"reactor cn cfg1 n={n} ld={ld}", "Y scaled", eY, 1e-12)
+    record(f"reactor cn cfg1 n={n} ld={ld}", "T relative", eT, 1e-12)
+    assert eY <= 1e-12 and eT <= 1e-12
+
+
 def test_cn_step_past_64_species(tmp_path):
     """66 species (the solve's one-cell-per-lane form, past the 64 of the
     one-cell-per-wavefront form): 33 isomer pairs A_i <-> B_i and the
