@@ -17,7 +17,7 @@
 namespace pyro {
 namespace {
 
-constexpr int kTBlock = 128;   // lanes per workgroup
+constexpr int kTBlock = 256;   // lanes per workgroup
 
 __device__ inline double poly5(cptr<double> a, double L) {
     return fma(L, fma(L, fma(L, fma(L, a[4], a[3]), a[2]), a[1]), a[0]);
@@ -106,7 +106,11 @@ hipError_t launch_transport(const pyro_mech* m, const TransportTables& tt, int64
                             int64_t ld, const double* T, const double* Y, double* mu,
                             double* kappa, double* D, hipStream_t stream) {
     const unsigned blocks = unsigned((n + kTBlock - 1) / kTBlock);
-    hipLaunchKernelGGL(transport_kernel<16>, dim3(blocks), dim3(kTBlock), 0, stream, m->dev, tt,
+    // blocks of four species: 58 VGPRs, eight waves per SIMD to cover the
+    // scalar loads of the pair records (2^20 config-1 cells: 3.78 ms, against
+    // 3.85 with 128-lane workgroups, 4.0 with blocks of 6, 4.25 of 8, 4.55
+    // of 2 and 5.49 of 16 at three waves per SIMD)
+    hipLaunchKernelGGL(transport_kernel<4>, dim3(blocks), dim3(kTBlock), 0, stream, m->dev, tt,
                        n, ld, T, Y, mu, kappa, D);
     return hipGetLastError();
 }
