@@ -22,9 +22,10 @@ struct Mixture {
     double xsum;
 };
 
+// (ysum, when given, receives sum_k Y_k from the same pass)
 template <int NG>
 __device__ inline void fold(const DevMech& m, const double* __restrict__ Y, int64_t ld,
-                            int64_t c, Mixture& mx) {
+                            int64_t c, Mixture& mx, double* ysum = nullptr) {
 #pragma unroll
     for (int g = 0; g < NG; ++g)
 #pragma unroll
@@ -32,9 +33,12 @@ __device__ inline void fold(const DevMech& m, const double* __restrict__ Y, int6
 #pragma unroll
             for (int q = 0; q < 6; ++q) mx.A[g][r][q] = 0.0;
     mx.xsum = 0.0;
+    double ys = 0.0;
     for (int k = 0; k < m.S; ++k) {
         const NewtonSpecies& s = m.newton[k];
-        const double X = Y[size_t(k) * ld + c] * s.inv_w;
+        const double y = Y[size_t(k) * ld + c];
+        const double X = y * s.inv_w;
+        ys += y;
         mx.xsum += X;
 #pragma unroll
         for (int g = 0; g < NG; ++g) {
@@ -47,6 +51,7 @@ __device__ inline void fold(const DevMech& m, const double* __restrict__ Y, int6
             }
         }
     }
+    if (ysum) *ysum = ys;
 }
 
 // Divides the folded coefficients by d (a fold over partial densities
@@ -137,9 +142,8 @@ __global__ __launch_bounds__(kBlock) void newton_kernel(
 // equation-of-state routine (Sec. "Python Code Generation and Immediate
 // Execution using NumPy"): rho = sum_k rho_k, Y_k = rho_k/rho, u = m/rho,
 // e = E/rho - |u|^2/2, T by the Newton inversion of e, p = rho R T/W.  The
-// partial densities are read twice (the second pass from cache): once to
-// form rho and the energy fold (over rho_k/W_k, then divided by rho), once to
-// write Y.
+// partial densities are read twice: once to form rho and the energy fold
+// (over rho_k/W_k, then divided by rho) in one pass, once to write Y.
 template <int NG>
 __global__ __launch_bounds__(kBlock) void primitive_kernel(
     DevMech m, int64_t n, int64_t ld, int dim, const double* __restrict__ rhok,
@@ -151,9 +155,8 @@ __global__ __launch_bounds__(kBlock) void primitive_kernel(
     const bool valid = i < n;
     const int64_t c = valid ? i : n - 1;
     Mixture mx;
-    fold<NG>(m, rhok, ld, c, mx);   // coefficients weighted by rho_k/W_k
-    double rho = 0.0;
-    for (int k = 0; k < m.S; ++k) rho += rhok[size_t(k) * ld + c];
+    double rho;
+    fold<NG>(m, rhok, ld, c, mx, &rho);   // coefficients weighted by rho_k/W_k
     scale<NG>(mx, rho);             // now weighted by Y_k/W_k; xsum = 1/W
     double kin = 0.0;
     for (int d = 0; d < dim; ++d) {
