@@ -54,6 +54,41 @@ __device__ inline void fold(const DevMech& m, const double* __restrict__ Y, int6
     if (ysum) *ysum = ys;
 }
 
+// fold over values already in registers, y[k] for k < S <= NR (same
+// arithmetic and order as fold)
+template <int NG, int NR>
+__device__ inline void fold_values(const DevMech& m, const double* y, Mixture& mx,
+                                   double* ysum) {
+#pragma unroll
+    for (int g = 0; g < NG; ++g)
+#pragma unroll
+        for (int r = 0; r < 2; ++r)
+#pragma unroll
+            for (int q = 0; q < 6; ++q) mx.A[g][r][q] = 0.0;
+    mx.xsum = 0.0;
+    double ys = 0.0;
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+        if (k < m.S) {
+            const NewtonSpecies& s = m.newton[k];
+            const double X = y[k] * s.inv_w;
+            ys += y[k];
+            mx.xsum += X;
+#pragma unroll
+            for (int g = 0; g < NG; ++g) {
+                if (s.group == g) {
+#pragma unroll
+                    for (int q = 0; q < 6; ++q) {
+                        mx.A[g][0][q] = fma(X, s.lo[q], mx.A[g][0][q]);
+                        mx.A[g][1][q] = fma(X, s.hi[q], mx.A[g][1][q]);
+                    }
+                }
+            }
+        }
+    }
+    *ysum = ys;
+}
+
 // Divides the folded coefficients by d (a fold over partial densities
 // rho_k then gives the fold over Y_k = rho_k/rho).
 template <int NG>
@@ -142,9 +177,10 @@ __global__ __launch_bounds__(kBlock) void newton_kernel(
 // equation-of-state routine (Sec. "Python Code Generation and Immediate
 // Execution using NumPy"): rho = sum_k rho_k, Y_k = rho_k/rho, u = m/rho,
 // e = E/rho - |u|^2/2, T by the Newton inversion of e, p = rho R T/W.  The
-// partial densities are read twice: once to form rho and the energy fold
-// (over rho_k/W_k, then divided by rho) in one pass, once to write Y.
-template <int NG>
+// partial densities are read once to form rho and the energy fold (over
+// rho_k/W_k, then divided by rho) in one pass; with NR > 0 (S <= NR) they stay
+// in registers for Y, else they are read again to write Y.
+template <int NG, int NR>
 __global__ __launch_bounds__(kBlock) void primitive_kernel(
     DevMech m, int64_t n, int64_t ld, int dim, const double* __restrict__ rhok,
     const double* __restrict__ mom, const double* __restrict__ E,
@@ -156,7 +192,15 @@ __global__ __launch_bounds__(kBlock) void primitive_kernel(
     const int64_t c = valid ? i : n - 1;
     Mixture mx;
     double rho;
-    fold<NG>(m, rhok, ld, c, mx, &rho);   // coefficients weighted by rho_k/W_k
+    double rk[NR > 0 ? NR : 1];
+    if constexpr (NR > 0) {
+        // all loads issued together (species past S read species S - 1)
+#pragma unroll
+        for (int k = 0; k < NR; ++k) rk[k] = rhok[size_t(k < m.S ? k : m.S - 1) * ld + c];
+        fold_values<NG, NR>(m, rk, mx, &rho);
+    } else {
+        fold<NG>(m, rhok, ld, c, mx, &rho);   // coefficients weighted by rho_k/W_k
+    }
     scale<NG>(mx, rho);             // now weighted by Y_k/W_k; xsum = 1/W
     double kin = 0.0;
     for (int d = 0; d < dim; ++d) {
@@ -169,7 +213,13 @@ __global__ __launch_bounds__(kBlock) void primitive_kernel(
     const double T = newton_solve<NG, false>(m, mx, e * (1.0 / kGasConstant),
                                              Tg ? Tg[c] : Tg_value, valid, max_iter, rtol, st);
     if (!valid) return;
-    for (int k = 0; k < m.S; ++k) Y_out[size_t(k) * ld + i] = rhok[size_t(k) * ld + i] / rho;
+    if constexpr (NR > 0) {
+#pragma unroll
+        for (int k = 0; k < NR; ++k)
+            if (k < m.S) Y_out[size_t(k) * ld + i] = rk[k] / rho;
+    } else {
+        for (int k = 0; k < m.S; ++k) Y_out[size_t(k) * ld + i] = rhok[size_t(k) * ld + i] / rho;
+    }
     rho_out[i] = rho;
     T_out[i] = T;
     p_out[i] = rho * kGasConstant * T * mx.xsum;
@@ -251,14 +301,17 @@ hipError_t launch_primitive(const pyro_mech* m, int64_t n, int64_t ld, int dim,
                             const double* T_guess, double T_guess_value, double* rho_out,
                             double* Y_out, double* u_out, double* T_out, double* p_out,
                             int32_t* status, int max_iter, double rtol, hipStream_t stream) {
-    if (m->dev.n_groups == 1)
-        hipLaunchKernelGGL(primitive_kernel<1>, dim3(grid(n)), dim3(kBlock), 0, stream, m->dev,
-                           n, ld, dim, rhok, mom, E, T_guess, T_guess_value, rho_out, Y_out, u_out,
-                           T_out, p_out, status, max_iter, rtol);
-    else
-        hipLaunchKernelGGL(primitive_kernel<kMaxTmidGroups>, dim3(grid(n)), dim3(kBlock), 0,
-                           stream, m->dev, n, ld, dim, rhok, mom, E, T_guess, T_guess_value,
-                           rho_out, Y_out, u_out, T_out, p_out, status, max_iter, rtol);
+    // partial densities held in registers up to 64 species with one T_mid
+    // group (one read of them); several groups' folds leave no room for them
+    const int S = m->S;
+    const auto k = m->dev.n_groups != 1 ? primitive_kernel<kMaxTmidGroups, 0>
+                 : S <= 32              ? primitive_kernel<1, 32>
+                 : S <= 56              ? primitive_kernel<1, 56>
+                 : S <= 64              ? primitive_kernel<1, 64>
+                                        : primitive_kernel<1, 0>;
+    hipLaunchKernelGGL(k, dim3(grid(n)), dim3(kBlock), 0, stream, m->dev, n, ld, dim, rhok, mom, E,
+                       T_guess, T_guess_value, rho_out, Y_out, u_out, T_out, p_out, status,
+                       max_iter, rtol);
     return hipGetLastError();
 }
 

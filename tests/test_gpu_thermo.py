@@ -16,7 +16,7 @@ pytestmark = pytest.mark.gpu
 def lib_mechs():
     torch = torch_cuda()
     import paper_2503_24286_amd as pyro
-    out = {c: pyro.Mechanism(mechs.config_path(c)) for c in (0, 1)}
+    out = {c: pyro.Mechanism(mechs.config_path(c)) for c in (0, 1, 3)}
     yield torch, pyro, out
     for m in out.values():
         m.close()
@@ -121,10 +121,11 @@ def test_temperature_from_enthalpy_matches_oracle(lib_mechs, cfg, n):
 
 
 @pytest.mark.parametrize("dim", [0, 1, 3])
-@pytest.mark.parametrize("cfg,n", [(0, 1000), (1, 2000 + 13)])
+@pytest.mark.parametrize("cfg,n", [(0, 1000), (1, 2000 + 13), (3, 700)])
 def test_primitive_from_conserved_matches_oracle(lib_mechs, cfg, n, dim):
     """rho, Y, u, T, p from (rho_k, rho u, E) against the oracle's routine,
-    with padded rows (ld > n) left untouched."""
+    with padded rows (ld > n) left untouched (configs 0 and 1 hold the
+    partial densities in registers, config 3's 160 species are read twice)."""
     from oracle import primitive
     torch, pyro, gms = lib_mechs
     m = mechs.load_config(cfg)
