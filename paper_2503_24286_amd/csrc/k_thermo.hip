@@ -34,9 +34,8 @@ __device__ inline void fold(const DevMech& m, const double* __restrict__ Y, int6
             for (int q = 0; q < 6; ++q) mx.A[g][r][q] = 0.0;
     mx.xsum = 0.0;
     double ys = 0.0;
-    for (int k = 0; k < m.S; ++k) {
+    auto add = [&](int k, double y) {
         const NewtonSpecies& s = m.newton[k];
-        const double y = Y[size_t(k) * ld + c];
         const double X = y * s.inv_w;
         ys += y;
         mx.xsum += X;
@@ -50,7 +49,17 @@ __device__ inline void fold(const DevMech& m, const double* __restrict__ Y, int6
                 }
             }
         }
+    };
+    // eight loads in flight at a time, then their terms in species order
+    int k = 0;
+    for (; k + 8 <= m.S; k += 8) {
+        double y[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) y[u] = Y[size_t(k + u) * ld + c];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) add(k + u, y[u]);
     }
+    for (; k < m.S; ++k) add(k, Y[size_t(k) * ld + c]);
     if (ysum) *ysum = ys;
 }
 
